@@ -1,0 +1,200 @@
+"""Throughput of the fused two-lattice DDF step on one MI355X.
+
+Workload: the periodic 8192 x 8192 decaying vortex field (seeded random Fourier
+velocity modes 4 <= |k| <= 16 with max |u| = 0.02, 1024 Gaussian scalar blobs with
+sigma = 32 cells), FP32 offset population storage, FP32 compute, tau = 0.8,
+tau_phi = 0.7, beta = (1, 0.9).  One benchmark step is one pass of the hot path:
+100 fused stream-and-collide time steps of both lattices, one FP64 reduction
+(mass, scalar, residual, non-finite count) and one extraction of rho, u, phi, S and
+omega.  `value` is MLUPS: fluid+scalar node-updates per second / 1e6, inputs
+resident in HBM.  The roofline object reports the step kernel's algorithmic HBM
+bandwidth (144 B per node-update in FP32: 18 populations read and written) from
+HIP events around its launches, against the 8 TB/s HBM3E peak.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+LB_STEPS_PER_STEP = 100
+BYTES_PER_NODE = {"f64": 288, "f32": 144, "f16": 72, "bf16": 72}
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_vortex8192_f32_counters.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1908_06742_amd", "csrc", n) for n in ("ddf.hip", "ddf_device.hpp")]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(nodes):
+    """HBM bytes per step launch from the committed rocprofv3 counter summary, or None
+    when the kernel sources changed since the counters were taken."""
+    try:
+        d = json.load(open(COUNTERS_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_hash() or d.get("nodes") != nodes:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP):
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1908_06742_amd import Lattice
+
+    vf = W.VortexField(L=L) if L == 8192 else W.VortexField(L=L, sigma=32.0 * L / 8192, n_blobs=max(16, 1024 * L * L // (8192 * 8192)))
+    pr = W.vortex_problem(L, storage=storage)
+    fields = vf.eval_grid(np.arange(L), np.arange(L), device="cuda")
+    lat = Lattice(pr, device="cuda").init(*fields)
+    del fields
+    out = torch.empty((16, L, L), dtype=torch.float32, device="cuda")
+    names = ["rho", "ux", "uy", "phi", "Sxx", "Syy", "Sxy", "wz"]
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def one(kernel_events=None):
+        if kernel_events is not None:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        lat.step(lb_steps)
+        if kernel_events is not None:
+            e1.record(stream)
+            kernel_events.append((e0, e1))
+        lat.reduce()       # synchronises the stream
+        lat.extract(names, out=out)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one(evs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms = sum(a.elapsed_time(b) for a, b in evs) / (steps * lb_steps)
+    stats = lat.reduce()
+    nodes = L * L
+    return {
+        "nodes": nodes,
+        "seconds": dt,
+        "mlups": nodes * lb_steps * steps / dt / 1e6,
+        "ms_per_step": 1e3 * dt / steps,
+        "kernel_ms": kern_ms,
+        "stats": stats,
+    }
+
+
+def cpu_baseline(budget_s=12.0):
+    """The FP64 oracle timed on the host cores on a bounded sample of the same
+    workload: a 256 x 256 window of the vortex field run as a periodic lattice, in
+    chunks of 20 steps until the time budget is spent."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+
+    n = 256
+    nthreads = os.cpu_count() or 1
+    vf = W.VortexField(L=8192)
+    pr = W.vortex_problem(n, storage="f64")
+    o = oracle.Oracle(pr, nthreads=nthreads)
+    f, g = o.init(*vf.fields(0, 0, n, n))
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        o.step(f, g, 20, steps)
+        steps += 20
+    dt = time.perf_counter() - t0
+    return {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": nthreads, "kind": "oracle",
+            "sample": f"FP64 oracle, {n}x{n} window of the 8192^2 vortex field run as a periodic lattice, {steps} steps, "
+                      f"{dt:.1f} s on {nthreads} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--size", type=int, default=8192)
+    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", action="store_true", help="also time FP16/BF16/FP64 storage and the 1024^2 cavity")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (the method's sharding "
+              "is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    print(f"[bench] {args.size}^2 {args.storage}: warmup {args.warmup}, timed {args.steps} steps "
+          f"x {LB_STEPS_PER_STEP} LB steps", file=sys.stderr, flush=True)
+    r = run_gpu(args.size, args.storage, args.steps, args.warmup)
+    nodes = r["nodes"]
+    bpn = BYTES_PER_NODE[args.storage]
+    achieved = bpn * nodes / (r["kernel_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(nodes) if args.storage == "f32" and args.size == 8192 else None
+    line = {
+        "metric": "MLUPS (fluid+scalar D2Q9 node-updates per second / 1e6)",
+        "value": round(r["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {
+            "workload": f"periodic {args.size}x{args.size} decaying vortex field, {args.storage} offset population "
+                        f"storage, {'f64' if args.storage == 'f64' else 'f32'} compute; one step = "
+                        f"{LB_STEPS_PER_STEP} fused two-lattice LB steps + FP64 reduction + extraction",
+            "nx": args.size, "ny": args.size, "lb_steps_per_step": LB_STEPS_PER_STEP,
+            "tau": 0.8, "tau_phi": 0.7, "beta": [1.0, 0.9],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"k_step<{args.storage}, MRT, periodic>",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": bpn * nodes,
+            "kernel_ms_per_launch": round(r["kernel_ms"], 4),
+        },
+        "final_stats": {k: r["stats"][k] for k in ("mass", "scalar", "res_u", "nonfinite")},
+    }
+    if args.variants:
+        var = []
+        for st, L in (("f16", 8192), ("bf16", 8192), ("f64", 8192)):
+            print(f"[bench] variant {L}^2 {st}", file=sys.stderr, flush=True)
+            v = run_gpu(L, st, 3, 1)
+            ach = BYTES_PER_NODE[st] * v["nodes"] / (v["kernel_ms"] * 1e-3) / 1e9
+            var.append({"storage": st, "size": L, "mlups": round(v["mlups"], 1),
+                        "kernel_gbs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4)})
+        line["variants"] = var
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

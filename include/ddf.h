@@ -1,0 +1,164 @@
+/*
+ * ddf.h - C ABI of libddf, the MI355X (gfx950) implementation of the
+ * double-distribution-function lattice Boltzmann method with local vorticity
+ * (Hajabdollahi & Premnath, arXiv:1908.06742).
+ *
+ * Two coupled D2Q9 lattices are advanced together:
+ *   - a fluid lattice f with the MRT collision in the natural raw-moment basis and
+ *     the trapezoidal body-force source (Sec. 2, eqs. MRT-LBEfluidmotion_transformed,
+ *     eqmrawmoment, the sigma' source list, hydrodynamic_fields);
+ *   - a passive-scalar lattice g with the MRT collision whose third-order
+ *     off-diagonal equilibria carry the anisotropy beta1 != beta2 (Sec. 3,
+ *     eqs. MRT-LBECDE, eqmrawmoment_CDE), or the SRT variant (App. B) or the
+ *     central-moment variants (App. C, App. D).
+ * The strain rate, spin, vorticity and scalar gradient are then extracted node by
+ * node from the second-order non-equilibrium moments of both lattices (Sec. 4,
+ * eqs. crossderivativeRHS1/2, offdiagvelderivativeresult1/2,
+ * diagvelderivativeresult1/2, vorticityexpression).
+ *
+ * Conventions for every entry point:
+ *   - All buffers are device memory allocated and owned by the caller; the library
+ *     never frees them.  The handle owns host-side state only.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *     Calls are asynchronous on that stream except ddf_reduce and
+ *     ddf_batch_reduce, which synchronise it to return host values.
+ *   - Return value: DDF_OK or a negative ddf_status.  No exception or abort crosses
+ *     the ABI; ddf_last_error() returns a thread-local message for the last error.
+ *   - Lattice units throughout (dx = dt = 1, Sec. 5).  Node (i, j) sits at x = i,
+ *     y = j; half-way walls lie at x = -1/2, x = nx - 1/2, y = -1/2, y = ny - 1/2.
+ *   - Dense field arrays are row-major [ny][nx] (x fastest).
+ */
+#ifndef DDF_H
+#define DDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Population storage format.  Populations are stored as offsets from the rest
+ * equilibrium, (f - f_eq(rho0, 0)) * pop_scale and (g - g_eq(phi0, 0)) * pop_scale;
+ * F64 computes in double, the others in float. */
+typedef enum { DDF_F64 = 0, DDF_F32 = 1, DDF_F16 = 2, DDF_BF16 = 3 } ddf_storage;
+
+typedef enum {
+    DDF_OK = 0,
+    DDF_ERR_ARG = -1,          /* invalid argument (message says which) */
+    DDF_ERR_UNSUPPORTED = -2,  /* valid request this build does not support */
+    DDF_ERR_HIP = -3,          /* a HIP runtime call failed */
+    DDF_ERR_NONFINITE = -4,    /* the state holds NaN or Inf */
+    DDF_ERR_STATE = -5         /* call out of order (e.g. step before init) */
+} ddf_status;
+
+enum { DDF_SIDE_LEFT = 0, DDF_SIDE_RIGHT = 1, DDF_SIDE_BOTTOM = 2, DDF_SIDE_TOP = 3 };
+
+/* Body force F(x, t): none; uniform (force[0], force[1]); four-rolls mill of Sec. 5.2,
+ * F = force[0] (sin k i sin k j, cos k i cos k j) with k = force_k; pulsatile of
+ * Sec. 5.3, F = (force[0], force[1]) cos(force_omega t). */
+enum { DDF_FORCE_NONE = 0, DDF_FORCE_UNIFORM = 1, DDF_FORCE_FOURROLL = 2, DDF_FORCE_PULSATILE = 3 };
+
+/* Scalar collision: MRT (Sec. 3), SRT (App. B), cascaded (App. C), non-cascaded
+ * central moments (App. D). */
+enum { DDF_SCALAR_MRT = 0, DDF_SCALAR_SRT = 1, DDF_SCALAR_CASCADED = 2, DDF_SCALAR_CENTRAL = 3 };
+
+/* Output planes of ddf_extract, in this order; bit k of the mask selects plane k.
+ * A_ij = d_j u_i (Sec. 1); S_xy = N_xy / 2; Omega_xy = -wz / 2.  The planar
+ * invariants Q, R and the Lamb vector L = omega x u are those of Sec. 1 with
+ * omega = (0, 0, wz). */
+enum {
+    DDF_OUT_RHO = 0, DDF_OUT_UX, DDF_OUT_UY, DDF_OUT_PHI,
+    DDF_OUT_SXX, DDF_OUT_SYY, DDF_OUT_SXY, DDF_OUT_WZ,
+    DDF_OUT_DXUY, DDF_OUT_DYUX, DDF_OUT_DXPHI, DDF_OUT_DYPHI,
+    DDF_OUT_Q, DDF_OUT_R, DDF_OUT_LX, DDF_OUT_LY,
+    DDF_NUM_OUTPUTS
+};
+
+/* Statistics returned by ddf_reduce (all from one FP64 pass over the state). */
+enum {
+    DDF_STAT_MASS = 0,        /* sum of rho */
+    DDF_STAT_SCALAR,          /* sum of phi */
+    DDF_STAT_RES_U,           /* |u^n - u^(n-K)|_2 / (K |u^n|_2), K = steps since the last reduce */
+    DDF_STAT_RES_PHI,         /* same for phi */
+    DDF_STAT_NONFINITE,       /* number of nodes with a non-finite rho, u or phi */
+    DDF_STAT_STEPS,           /* K */
+    DDF_STAT_UMAX,            /* max |u| */
+    DDF_STAT_PHIMIN,          /* min phi */
+    DDF_NUM_STATS
+};
+
+typedef struct {
+    int32_t nx, ny;              /* nodes; nx, ny >= 2 */
+    int32_t periodic_x;          /* 1 = periodic in x, 0 = half-way walls at x = -1/2, nx - 1/2 */
+    int32_t periodic_y;          /* same in y */
+    int32_t storage;             /* ddf_storage */
+    int32_t scalar_model;        /* DDF_SCALAR_* */
+    double omega[9];             /* fluid rates diag(0,0,0,w3..w8) (Sec. 2, eq. relaxationtimematrix_fluidmotion); [0..2] ignored */
+    double omega_phi[9];         /* scalar rates diag(0,w1..w8) (Sec. 3, eq. relaxationtimematrix_CDE); [0] ignored.
+                                    SRT uses omega_phi[1] for every population. */
+    double beta1, beta2;         /* scalar-flux anisotropy; |beta1 - beta2| must exceed 1e-12 */
+    double cs2, cs2_phi;         /* c_s^2 and c_sphi^2 (1/3 in the paper) */
+    double wall_u[4][2];         /* wall velocity per side (DDF_SIDE_*); used where that side is a wall */
+    double wall_phi[4];          /* Dirichlet scalar per side; NaN = zero-flux wall */
+    int32_t force_kind;          /* DDF_FORCE_* */
+    int32_t reserved0;
+    double force[2];
+    double force_k;
+    double force_omega;
+    double rho0, phi0;           /* offset references of the population storage */
+    double pop_scale;            /* power-of-two storage scale; 0 = library default (256 for F16, else 1) */
+    double phi_min;              /* |phi| < phi_min: wz, dxuy, dyux, Q, R, L are NaN (the phi = 0 singularity of Sec. 4) */
+} ddf_params;
+
+typedef struct ddf_handle ddf_handle;
+
+/* Row pitch in elements of every population plane (a multiple of 64). */
+int64_t ddf_pitch(const ddf_params *p);
+/* Bytes of one lattice's populations: 9 planes of pitch * ny storage elements.
+ * The caller allocates two such buffers (f and g). */
+size_t ddf_population_bytes(const ddf_params *p);
+/* Bytes of device workspace ddf_create needs (residual snapshot and reduction partials). */
+size_t ddf_workspace_bytes(const ddf_params *p);
+
+/* Validate p (tau > 1/2 equivalents: 0 < omega < 2 for omega3..8 and omega1^phi..8^phi,
+ * beta1 != beta2, nx, ny >= 2, known storage/model/force) and bind the caller's
+ * buffers.  pop_f, pop_g: ddf_population_bytes(p) each; workspace:
+ * ddf_workspace_bytes(p); all 256-byte aligned.  *out receives the handle. */
+int ddf_create(const ddf_params *p, void *pop_f, void *pop_g, void *workspace, ddf_handle **out);
+void ddf_destroy(ddf_handle *h);
+
+/* Equilibrium initial state from dense FP64 device fields rho, ux, uy, phi
+ * ([ny][nx] each): f = T^-1 (m_eq(rho, u) - S(F(x, 0), u) / 2), g = T^-1 n_eq(phi, u),
+ * so that the velocity recovered with the half-force shift (Sec. 2,
+ * eq. hydrodynamic_fields) equals u.  Resets the step counter to 0. */
+int ddf_init_equilibrium(ddf_handle *h, const double *rho, const double *ux, const double *uy,
+                         const double *phi, void *stream);
+
+/* Advance nsteps >= 0 time steps (collide both lattices, stream with walls). */
+int ddf_step(ddf_handle *h, int64_t nsteps, void *stream);
+
+/* Local kinematics of the current state (pre-collision populations at the current
+ * step, Sec. 4) into out: DDF_NUM_OUTPUTS dense planes of ny * nx elements of type
+ * out_dtype (0 = double, 1 = float); only planes whose bit is set in mask are written. */
+int ddf_extract(ddf_handle *h, void *out, uint32_t mask, int32_t out_dtype, void *stream);
+
+/* FP64 statistics of the current state into out[DDF_NUM_STATS] (host memory), and a
+ * new residual snapshot.  Synchronises the stream.  Returns DDF_ERR_NONFINITE (with
+ * out filled) when any node is non-finite. */
+int ddf_reduce(ddf_handle *h, double *out, void *stream);
+
+/* Logical populations of the current state, direction-major dense [9][ny][nx].
+ * dtype 0: absolute values as double; dtype 1: the raw stored offsets in the storage
+ * type (bitwise checkpoint). */
+int ddf_get_populations(ddf_handle *h, void *f, void *g, int32_t dtype, void *stream);
+/* Inverse of ddf_get_populations; the step counter becomes `step`. */
+int ddf_set_populations(ddf_handle *h, const void *f, const void *g, int32_t dtype, int64_t step, void *stream);
+
+int64_t ddf_step_count(const ddf_handle *h);
+const char *ddf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDF_H */

@@ -1,0 +1,18 @@
+"""MI355X (gfx950) implementation of the DDF lattice Boltzmann method with local
+vorticity extraction (Hajabdollahi & Premnath, arXiv:1908.06742).
+
+The method runs in HIP kernels behind the C ABI of ``libddf.so`` (include/ddf.h);
+this package is the thin Python binding over it.
+"""
+from ._lib import DDFError, OUTPUTS, STATS, lib  # noqa: F401
+
+
+def __getattr__(name):
+    # torch-dependent classes are imported on first use
+    if name == "Lattice":
+        from .lattice import Lattice
+        return Lattice
+    if name == "Batch":
+        from .batch import Batch
+        return Batch
+    raise AttributeError(name)

@@ -1,0 +1,117 @@
+"""Python face of libddf: one coupled fluid + scalar D2Q9 lattice on one GPU.
+
+Argument marshalling only: torch allocates the device buffers and supplies the
+stream; every step of the method runs in the HIP kernels behind the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+_TORCH_STORAGE = {L.DDF_F64: torch.float64, L.DDF_F32: torch.float32,
+                  L.DDF_F16: torch.float16, L.DDF_BF16: torch.bfloat16}
+
+
+def _stream_ptr(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr())
+
+
+class Lattice:
+    """A fluid lattice f and a scalar lattice g (caller-owned torch buffers).
+
+    ``problem`` is a workloads.Problem (or any object with its attributes).
+    """
+
+    def __init__(self, problem, device="cuda", stream=None):
+        lib = L.lib()
+        self.problem = problem
+        self.params = L.params_from_problem(problem)
+        self.device = torch.device(device)
+        self.stream = stream
+        nbytes = lib.ddf_population_bytes(C.byref(self.params))
+        wbytes = lib.ddf_workspace_bytes(C.byref(self.params))
+        if nbytes == 0 or wbytes == 0:
+            # validation failure: surface the library's message
+            h = C.c_void_p()
+            L.check(lib.ddf_create(C.byref(self.params), C.c_void_p(256), C.c_void_p(256), C.c_void_p(256), C.byref(h)))
+        self.pop_f = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.pop_g = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.workspace = torch.empty(wbytes, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        L.check(lib.ddf_create(C.byref(self.params), _ptr(self.pop_f), _ptr(self.pop_g), _ptr(self.workspace),
+                               C.byref(h)))
+        self._h = h
+        self.nx, self.ny = int(problem.nx), int(problem.ny)
+        self.pitch = int(lib.ddf_pitch(C.byref(self.params)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            L.lib().ddf_destroy(h)
+            self._h = None
+
+    # -- state -----------------------------------------------------------------
+    def _field(self, a):
+        t = torch.as_tensor(a, dtype=torch.float64)
+        t = torch.broadcast_to(t, (self.ny, self.nx)).to(self.device).contiguous()
+        return t
+
+    def init(self, rho, ux, uy, phi):
+        fields = [self._field(a) for a in (rho, ux, uy, phi)]
+        L.check(L.lib().ddf_init_equilibrium(self._h, *[_ptr(t) for t in fields], _stream_ptr(self.stream)))
+        self._keep = fields  # alive until the stream has consumed them
+        return self
+
+    def step(self, nsteps=1):
+        L.check(L.lib().ddf_step(self._h, int(nsteps), _stream_ptr(self.stream)))
+        return self
+
+    @property
+    def step_count(self):
+        return int(L.lib().ddf_step_count(self._h))
+
+    def extract(self, names=None, dtype=torch.float64, out=None):
+        """Local kinematics of the current state: dict name -> (ny, nx) tensor."""
+        names = list(L.OUTPUTS) if names is None else list(names)
+        mask = 0
+        for n in names:
+            mask |= 1 << L.OUTPUTS.index(n)
+        if out is None:
+            out = torch.empty((len(L.OUTPUTS), self.ny, self.nx), dtype=dtype, device=self.device)
+        od = 0 if out.dtype == torch.float64 else 1
+        L.check(L.lib().ddf_extract(self._h, _ptr(out), mask, od, _stream_ptr(self.stream)))
+        return {n: out[L.OUTPUTS.index(n)] for n in names}
+
+    def reduce(self, raise_nonfinite=True):
+        buf = (C.c_double * len(L.STATS))()
+        rc = L.lib().ddf_reduce(self._h, buf, _stream_ptr(self.stream))
+        stats = {k: buf[i] for i, k in enumerate(L.STATS)}
+        if rc == L.DDF_ERR_NONFINITE and not raise_nonfinite:
+            return stats
+        L.check(rc)
+        return stats
+
+    def get_populations(self, raw=False):
+        """(f, g) as (9, ny, nx): absolute float64 values, or the raw stored offsets."""
+        dt = _TORCH_STORAGE[self.params.storage] if raw else torch.float64
+        f = torch.empty((9, self.ny, self.nx), dtype=dt, device=self.device)
+        g = torch.empty_like(f)
+        L.check(L.lib().ddf_get_populations(self._h, _ptr(f), _ptr(g), 1 if raw else 0, _stream_ptr(self.stream)))
+        return f, g
+
+    def set_populations(self, f, g, step=0, raw=False):
+        dt = _TORCH_STORAGE[self.params.storage] if raw else torch.float64
+        f = torch.as_tensor(f).to(self.device, dt).contiguous()
+        g = torch.as_tensor(g).to(self.device, dt).contiguous()
+        L.check(L.lib().ddf_set_populations(self._h, _ptr(f), _ptr(g), 1 if raw else 0, int(step),
+                                            _stream_ptr(self.stream)))
+        self._keep = (f, g)
+        return self

@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared symbol,
+and validates its arguments before touching any device memory (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import workloads as W
+from conftest import ROOT
+from paper_1908_06742_amd import _lib as L
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ddf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ddf_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    names = declared_functions()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.SIGNATURES), "binding and header disagree"
+
+
+def _create(pr):
+    p = L.params_from_problem(pr)
+    h = C.c_void_p()
+    # fake aligned addresses: validation fails before they are used
+    rc = L.lib().ddf_create(C.byref(p), C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20), C.byref(h))
+    msg = L.lib().ddf_last_error().decode()
+    if rc == 0:
+        L.lib().ddf_destroy(h)
+    return rc, msg
+
+
+@pytest.mark.parametrize("bad,needle", [
+    (dict(beta2=1.0), "beta1 == beta2"),
+    (dict(nx=1), "nx and ny"),
+    (dict(tau=0.5), "(0, 2)"),
+    (dict(tau_phi=0.49), "(0, 2)"),
+    (dict(storage="f64", rho0=0.0), "rho0"),
+])
+def test_create_rejects_invalid_parameters(bad, needle):
+    pr = W.taylor_green_problem(16).with_(**bad)
+    rc, msg = _create(pr)
+    assert rc == L.DDF_ERR_ARG and needle in msg
+
+
+def test_create_rejects_non_power_of_two_scale():
+    pr = W.taylor_green_problem(16, storage="f16")
+    pr.pop_scale = 3.0
+    rc, msg = _create(pr)
+    assert rc == L.DDF_ERR_ARG and "power of two" in msg
+
+
+def test_create_rejects_unaligned_buffers():
+    p = L.params_from_problem(W.taylor_green_problem(16))
+    h = C.c_void_p()
+    rc = L.lib().ddf_create(C.byref(p), C.c_void_p(1 << 20 | 8), C.c_void_p(2 << 20), C.c_void_p(3 << 20), C.byref(h))
+    assert rc == L.DDF_ERR_ARG and "aligned" in L.lib().ddf_last_error().decode()
+
+
+def test_valid_create_and_sizes():
+    for storage, s in (("f64", 8), ("f32", 4), ("f16", 2), ("bf16", 2)):
+        pr = W.Problem(nx=100, ny=37, storage=storage)
+        p = L.params_from_problem(pr)
+        pitch = L.lib().ddf_pitch(C.byref(p))
+        assert pitch == 128
+        nb = L.lib().ddf_population_bytes(C.byref(p))
+        assert nb >= 9 * pitch * 37 * s and nb % 256 == 0
+        assert L.lib().ddf_workspace_bytes(C.byref(p)) > 3 * 100 * 37 * 4
+        rc, msg = _create(pr)
+        assert rc == 0, msg
+
+
+def test_step_before_init_is_a_state_error():
+    p = L.params_from_problem(W.taylor_green_problem(16))
+    h = C.c_void_p()
+    assert L.lib().ddf_create(C.byref(p), C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20), C.byref(h)) == 0
+    try:
+        assert L.lib().ddf_step(h, 1, None) == L.DDF_ERR_STATE
+        assert L.lib().ddf_step(h, -1, None) == L.DDF_ERR_ARG
+        buf = (C.c_double * 8)()
+        assert L.lib().ddf_reduce(h, buf, None) == L.DDF_ERR_STATE
+    finally:
+        L.lib().ddf_destroy(h)
