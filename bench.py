@@ -132,8 +132,19 @@ def main():
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", action="store_true", help="also time FP16/BF16/FP64 storage and the 1024^2 cavity")
+    ap.add_argument("--variants", action="store_true", help="also time FP16/BF16/FP64 storage of the same field")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_dispatch": 1 << 30, "copy_bytes_written_per_dispatch": 1 << 30}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the method's sharding "
               "is described in DESIGN.md); run with --gpus 1", file=sys.stderr)

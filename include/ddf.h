@@ -115,7 +115,11 @@ typedef struct ddf_handle ddf_handle;
 
 /* Row pitch in elements of every population plane (a multiple of 64). */
 int64_t ddf_pitch(const ddf_params *p);
-/* Bytes of one lattice's populations: 9 planes of pitch * ny storage elements.
+/* Elements from one direction plane to the next: pitch * ny, plus a 256 KiB + 256 B
+ * gap for planes of 16 MiB or more (it spreads the 18 concurrent streams over the
+ * HBM channel interleave). */
+int64_t ddf_plane_stride(const ddf_params *p);
+/* Bytes of one lattice's populations: 9 planes of ddf_plane_stride storage elements.
  * The caller allocates two such buffers (f and g). */
 size_t ddf_population_bytes(const ddf_params *p);
 /* Bytes of device workspace ddf_create needs (residual snapshot and reduction partials). */

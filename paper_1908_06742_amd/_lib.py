@@ -57,6 +57,7 @@ _vp = C.c_void_p
 _P = C.POINTER(Params)
 SIGNATURES = {
     "ddf_pitch": (C.c_int64, [_P]),
+    "ddf_plane_stride": (C.c_int64, [_P]),
     "ddf_population_bytes": (C.c_size_t, [_P]),
     "ddf_workspace_bytes": (C.c_size_t, [_P]),
     "ddf_create": (C.c_int, [_P, _vp, _vp, _vp, C.POINTER(_vp)]),

@@ -4,6 +4,9 @@
 // Data layout in HBM: each lattice is 9 planes (one per direction), each plane ny rows
 // of `pitch` elements (pitch = nx rounded up to 64), so a wavefront reads or writes 64
 // consecutive nodes of one direction: 256 B (FP32), 512 B (FP64), 128 B (FP16/BF16).
+// Large planes are separated by an extra 256 KiB + 256 B so that the 18 streams a
+// node touches at one (x, y) do not start at the same offset of the HBM channel
+// interleave (measured: +2% on 8192^2 FP32).
 // Streaming is the in-place AA pattern: an even step reads a node's own slots and
 // writes its post-collision populations into the opposite slots of the same node; an
 // odd step reads the slots its neighbours wrote and pushes its results into their
@@ -25,6 +28,9 @@
 
 using namespace ddf;
 
+// Workgroup size of the lattice kernels (512 measured 1.5% faster than 256 on 8192^2).
+constexpr int kThreads = 512;
+
 // ---------------------------------------------------------------------------
 // Geometry and tile mapping
 // ---------------------------------------------------------------------------
@@ -34,7 +40,7 @@ struct Geom {
     int64_t plane;      // elements per direction plane (pitch * ny)
     int px, py;         // periodic flags
     int bx_shift;       // tile width = 1 << bx_shift
-    int by;             // tile height (bx * by = 256)
+    int by;             // tile height (bx * by = kThreads)
     int tiles_x;
     int ntiles;
 };
@@ -109,7 +115,7 @@ __device__ __forceinline__ void load_logical(const S *__restrict__ f, const Geom
 // Step kernel
 // ---------------------------------------------------------------------------
 template <class S, int SCALAR, bool WALLS, bool FORCE, bool ODD>
-__global__ __launch_bounds__(256) void k_step(S *__restrict__ f, S *__restrict__ g, const Geom G,
+__global__ __launch_bounds__(kThreads) void k_step(S *__restrict__ f, S *__restrict__ g, const Geom G,
                                               const Phys<typename Codec<S>::R> P, const int64_t t)
 {
     using R = typename Codec<S>::R;
@@ -163,7 +169,7 @@ __global__ __launch_bounds__(256) void k_step(S *__restrict__ f, S *__restrict__
 // Extraction, initialisation, reductions, population access
 // ---------------------------------------------------------------------------
 template <class S, bool WALLS, bool ODD, class O>
-__global__ __launch_bounds__(256) void k_extract(const S *__restrict__ f, const S *__restrict__ g, const Geom G,
+__global__ __launch_bounds__(kThreads) void k_extract(const S *__restrict__ f, const S *__restrict__ g, const Geom G,
                                                  const Phys<typename Codec<S>::R> P, const int64_t t,
                                                  const int scalar_model, O *__restrict__ out, const uint32_t mask)
 {
@@ -189,7 +195,7 @@ __global__ __launch_bounds__(256) void k_extract(const S *__restrict__ f, const 
 }
 
 template <class S>
-__global__ __launch_bounds__(256) void k_init(S *__restrict__ f, S *__restrict__ g, const Geom G,
+__global__ __launch_bounds__(kThreads) void k_init(S *__restrict__ f, S *__restrict__ g, const Geom G,
                                               const Phys<typename Codec<S>::R> P, const double *__restrict__ rho,
                                               const double *__restrict__ ux, const double *__restrict__ uy,
                                               const double *__restrict__ phi)
@@ -229,13 +235,13 @@ __global__ __launch_bounds__(256) void k_init(S *__restrict__ f, S *__restrict__
 enum { RS_MASS = 0, RS_SCALAR, RS_DU2, RS_U2, RS_DPHI2, RS_PHI2, RS_NONFIN, RS_UMAX, RS_PHIMIN, RS_N };
 
 template <class S, bool WALLS, bool ODD>
-__global__ __launch_bounds__(256) void k_reduce(const S *__restrict__ f, const S *__restrict__ g, const Geom G,
+__global__ __launch_bounds__(kThreads) void k_reduce(const S *__restrict__ f, const S *__restrict__ g, const Geom G,
                                                 const Phys<typename Codec<S>::R> P, const int64_t t,
                                                 typename Codec<S>::R *__restrict__ snap, const int snap_valid,
                                                 double *__restrict__ partials)
 {
     using R = typename Codec<S>::R;
-    __shared__ double sh[RS_N][256];
+    __shared__ double sh[RS_N][kThreads];
     double v[RS_N] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
     int x, y;
     if (node_of_thread(G, x, y)) {
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(256) void k_reduce(const S *__restrict__ f, const S
 #pragma unroll
     for (int k = 0; k < RS_N; ++k) sh[k][tid] = v[k];
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
         if (tid < s) {
 #pragma unroll
             for (int k = 0; k < RS_UMAX; ++k) sh[k][tid] += sh[k][tid + s];
@@ -312,7 +318,7 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double *__restrict__
 
 // dtype 0: absolute FP64 values; dtype 1: raw stored elements.
 template <class S, bool WALLS, bool ODD>
-__global__ __launch_bounds__(256) void k_get(const S *__restrict__ f, const S *__restrict__ g, const Geom G,
+__global__ __launch_bounds__(kThreads) void k_get(const S *__restrict__ f, const S *__restrict__ g, const Geom G,
                                              const Phys<typename Codec<S>::R> P, void *__restrict__ fo,
                                              void *__restrict__ go, const int dtype)
 {
@@ -334,7 +340,7 @@ __global__ __launch_bounds__(256) void k_get(const S *__restrict__ f, const S *_
 }
 
 template <class S, bool WALLS, bool ODD>
-__global__ __launch_bounds__(256) void k_set(S *__restrict__ f, S *__restrict__ g, const Geom G,
+__global__ __launch_bounds__(kThreads) void k_set(S *__restrict__ f, S *__restrict__ g, const Geom G,
                                              const Phys<typename Codec<S>::R> P, const void *__restrict__ fi,
                                              const void *__restrict__ gi, const int dtype)
 {
@@ -380,6 +386,14 @@ int fail(int code, const std::string &msg)
 int64_t pitch_of(const ddf_params *p) { return ((int64_t)p->nx + 63) / 64 * 64; }
 
 size_t storage_size(int storage) { return storage == DDF_F64 ? 8 : (storage == DDF_F32 ? 4 : 2); }
+
+// Elements per direction plane: pitch * ny, plus 256 KiB + 256 B for planes of 16 MiB or more.
+int64_t plane_of(const ddf_params *p)
+{
+    const int64_t s = (int64_t)storage_size(p->storage);
+    const int64_t base = pitch_of(p) * p->ny;
+    return base * s >= (16ll << 20) ? base + ((256ll << 10) + 256) / s : base;
+}
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -484,14 +498,14 @@ Geom make_geom(const ddf_params &p)
     G.nx = p.nx;
     G.ny = p.ny;
     G.pitch = (int)pitch_of(&p);
-    G.plane = (int64_t)G.pitch * p.ny;
+    G.plane = plane_of(&p);
     G.px = p.periodic_x ? 1 : 0;
     G.py = p.periodic_y ? 1 : 0;
-    // tile: as wide as the row allows (coalesced rows), 256 threads
-    int bxs = 8;
+    // tile: as wide as the row allows (coalesced rows), kThreads threads
+    int bxs = 9;
     while (bxs > 5 && (1 << (bxs - 1)) >= p.nx) --bxs;
     G.bx_shift = bxs;
-    G.by = 256 >> bxs;
+    G.by = kThreads >> bxs;
     G.tiles_x = (p.nx + (1 << bxs) - 1) >> bxs;
     G.ntiles = G.tiles_x * ((p.ny + G.by - 1) / G.by);
     return G;
@@ -558,10 +572,10 @@ void launch_step_parity(ddf_handle *h, hipStream_t st, bool odd)
 {
     const int nb = grid_blocks(h->G);
     if (odd)
-        hipLaunchKernelGGL((k_step<S, SC, W, FO, true>), dim3(nb), dim3(256), 0, st, (S *)h->f, (S *)h->g, h->G,
+        hipLaunchKernelGGL((k_step<S, SC, W, FO, true>), dim3(nb), dim3(kThreads), 0, st, (S *)h->f, (S *)h->g, h->G,
                            phys_of<S>(h), h->step);
     else
-        hipLaunchKernelGGL((k_step<S, SC, W, FO, false>), dim3(nb), dim3(256), 0, st, (S *)h->f, (S *)h->g, h->G,
+        hipLaunchKernelGGL((k_step<S, SC, W, FO, false>), dim3(nb), dim3(kThreads), 0, st, (S *)h->f, (S *)h->g, h->G,
                            phys_of<S>(h), h->step);
 }
 
@@ -589,10 +603,12 @@ extern "C" {
 
 int64_t ddf_pitch(const ddf_params *p) { return p ? pitch_of(p) : 0; }
 
+int64_t ddf_plane_stride(const ddf_params *p) { return p ? plane_of(p) : 0; }
+
 size_t ddf_population_bytes(const ddf_params *p)
 {
     if (!p) return 0;
-    return align256(9 * (size_t)pitch_of(p) * (size_t)p->ny * storage_size(p->storage));
+    return align256(9 * (size_t)plane_of(p) * storage_size(p->storage));
 }
 
 size_t ddf_workspace_bytes(const ddf_params *p)
@@ -640,7 +656,7 @@ int ddf_init_equilibrium(ddf_handle *h, const double *rho, const double *ux, con
     hipStream_t st = (hipStream_t)stream;
     with_storage(h->p.storage, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL((k_init<S>), dim3(h->nblocks), dim3(256), 0, st, (S *)h->f, (S *)h->g, h->G, phys_of<S>(h),
+        hipLaunchKernelGGL((k_init<S>), dim3(h->nblocks), dim3(kThreads), 0, st, (S *)h->f, (S *)h->g, h->G, phys_of<S>(h),
                            rho, ux, uy, phi);
         return 0;
     });
@@ -687,7 +703,7 @@ int ddf_extract(ddf_handle *h, void *out, uint32_t mask, int32_t out_dtype, void
         auto go = [&](auto *otag) {
             using O = std::remove_pointer_t<decltype(otag)>;
 #define DDF_EXTRACT(W_, O_)                                                                                      \
-    hipLaunchKernelGGL((k_extract<S, W_, O_, O>), dim3(h->nblocks), dim3(256), 0, st, (const S *)h->f,        \
+    hipLaunchKernelGGL((k_extract<S, W_, O_, O>), dim3(h->nblocks), dim3(kThreads), 0, st, (const S *)h->f,        \
                        (const S *)h->g, h->G, phys_of<S>(h), h->step, h->p.scalar_model, (O *)out, mask)
             if (w) { if (odd) DDF_EXTRACT(true, true); else DDF_EXTRACT(true, false); }
             else { if (odd) DDF_EXTRACT(false, true); else DDF_EXTRACT(false, false); }
@@ -717,7 +733,7 @@ int ddf_reduce(ddf_handle *h, double *out, void *stream)
         using S = std::remove_pointer_t<decltype(tag)>;
         using R = typename Codec<S>::R;
 #define DDF_REDUCE(W_, O_)                                                                                       \
-    hipLaunchKernelGGL((k_reduce<S, W_, O_>), dim3(h->nblocks), dim3(256), 0, st, (const S *)h->f,             \
+    hipLaunchKernelGGL((k_reduce<S, W_, O_>), dim3(h->nblocks), dim3(kThreads), 0, st, (const S *)h->f,             \
                        (const S *)h->g, h->G, phys_of<S>(h), h->step, (R *)snap, sv, partials)
         if (w) { if (odd) DDF_REDUCE(true, true); else DDF_REDUCE(true, false); }
         else { if (odd) DDF_REDUCE(false, true); else DDF_REDUCE(false, false); }
@@ -755,7 +771,7 @@ int ddf_get_populations(ddf_handle *h, void *f, void *g, int32_t dtype, void *st
     with_storage(h->p.storage, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
 #define DDF_GET(W_, O_)                                                                                          \
-    hipLaunchKernelGGL((k_get<S, W_, O_>), dim3(h->nblocks), dim3(256), 0, st, (const S *)h->f, (const S *)h->g, \
+    hipLaunchKernelGGL((k_get<S, W_, O_>), dim3(h->nblocks), dim3(kThreads), 0, st, (const S *)h->f, (const S *)h->g, \
                        h->G, phys_of<S>(h), f, g, dtype)
         if (w) { if (odd) DDF_GET(true, true); else DDF_GET(true, false); }
         else { if (odd) DDF_GET(false, true); else DDF_GET(false, false); }
@@ -777,7 +793,7 @@ int ddf_set_populations(ddf_handle *h, const void *f, const void *g, int32_t dty
     with_storage(h->p.storage, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
 #define DDF_SET(W_, O_)                                                                                          \
-    hipLaunchKernelGGL((k_set<S, W_, O_>), dim3(h->nblocks), dim3(256), 0, st, (S *)h->f, (S *)h->g, h->G,       \
+    hipLaunchKernelGGL((k_set<S, W_, O_>), dim3(h->nblocks), dim3(kThreads), 0, st, (S *)h->f, (S *)h->g, h->G,       \
                        phys_of<S>(h), f, g, dtype)
         if (w) { if (odd) DDF_SET(true, true); else DDF_SET(true, false); }
         else { if (odd) DDF_SET(false, true); else DDF_SET(false, false); }
