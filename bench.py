@@ -98,6 +98,56 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP):
     }
 
 
+def run_cavity(n=1024, steps=20000):
+    """Lid-driven cavity n^2, Re = 1000, U = 0.1, FP32 offset storage, phi = 1 on the lid
+    and 0 on the other walls.  Its 75 MB of populations stay in the 256 MB Infinity
+    Cache, so this rate is not an HBM figure."""
+    import torch
+
+    import workloads as W
+    from paper_1908_06742_amd import Lattice
+
+    pr = W.cavity_problem(n, 1000.0, 0.1, storage="f32")
+    lat = Lattice(pr, device="cuda").init(*W.cavity_fields(n))
+    lat.step(200)
+    lat.reduce()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    s = lat.reduce()
+    dt = time.perf_counter() - t0
+    return {"mlups": round(n * n * steps / dt / 1e6, 1), "steps": steps, "seconds": round(dt, 3),
+            "res_u": s["res_u"], "res_phi": s["res_phi"], "nonfinite": s["nonfinite"]}
+
+
+def run_batch(steps=2000, count=256):
+    """256 cavities and channels of sides 64..512, Re 100..5000, U 0.05..0.1 (seeded),
+    FP32, autotuned tiling, graph-captured runs of 100 steps."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1908_06742_amd import Batch
+
+    inst = W.batch_instances(count)
+    b = Batch([i.problem for i in inst], device="cuda")
+    tune = b.autotune(steps_per_trial=10)
+    fields = [W.rest_fields(i.nx, i.ny, 1.0, 0.0 if i.kind == "cavity" else 0.5) for i in inst]
+    b.init(fields)
+    b.step(200)
+    b.reduce()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    s = b.reduce()
+    dt = time.perf_counter() - t0
+    nodes = b.total_nodes
+    return {"instances": count, "nodes": nodes, "mlups": round(nodes * steps / dt / 1e6, 1), "steps": steps,
+            "seconds": round(dt, 3), "tiling": b.tiling(), "autotune_ms_per_step": tune["ms_per_step"],
+            "nonfinite_instances": int(np.sum(s["nonfinite"] > 0)),
+            "hbm_gbs": round(144.0 * nodes * steps / dt / 1e9, 1)}
+
+
 def cpu_baseline(budget_s=12.0):
     """The FP64 oracle timed on the host cores on a bounded sample of the same
     workload: a 256 x 256 window of the vortex field run as a periodic lattice, in
@@ -132,6 +182,8 @@ def main():
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 1024^2 cavity and 256-instance batch lines")
+    ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--variants", action="store_true", help="also time FP16/BF16/FP64 storage of the same field")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (reference for HBM byte counters)")
@@ -192,6 +244,11 @@ def main():
         },
         "final_stats": {k: r["stats"][k] for k in ("mass", "scalar", "res_u", "nonfinite")},
     }
+    if not args.no_extras:
+        print("[bench] extra: cavity 1024^2 f32", file=sys.stderr, flush=True)
+        line["extras"] = {"cavity1024_f32": run_cavity()}
+        print("[bench] extra: batch of 256 instances f32", file=sys.stderr, flush=True)
+        line["extras"]["batch256_f32"] = run_batch(args.batch_steps)
     if args.variants:
         var = []
         for st, L in (("f16", 8192), ("bf16", 8192), ("f64", 8192)):

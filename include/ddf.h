@@ -162,6 +162,55 @@ int ddf_set_populations(ddf_handle *h, const void *f, const void *g, int32_t dty
 int64_t ddf_step_count(const ddf_handle *h);
 const char *ddf_last_error(void);
 
+/* ---------------------------------------------------------------------------------
+ * Batches: n independent lattices (own size, rates, walls, force) advanced together
+ * by one persistent launch per time step.  All instances share one storage type and
+ * one scalar collision model.  Instance i's populations sit at a 256-byte aligned
+ * offset of one f and one g buffer (ddf_batch_offsets); its dense fields sit at a
+ * node offset of concatenated [ny_i][nx_i] arrays.  Runs of K steps (default 100,
+ * ddf_batch_set_graph) are captured once into a hipGraph on an internal stream and
+ * replayed on the caller's stream; batches with a time-dependent force step eagerly.
+ * --------------------------------------------------------------------------------- */
+typedef struct ddf_batch ddf_batch;
+
+/* Bytes of the f (and of the g) buffer for n instances. */
+size_t ddf_batch_population_bytes(int32_t n, const ddf_params *ps);
+/* Bytes of device workspace (descriptors, tile list, reduction partials, snapshots). */
+size_t ddf_batch_workspace_bytes(int32_t n, const ddf_params *ps);
+/* Validate every instance as ddf_create does and bind the caller's buffers
+ * (256-byte aligned).  Uploads the instance descriptors (synchronous). */
+int ddf_batch_create(int32_t n, const ddf_params *ps, void *pop_f, void *pop_g, void *workspace, ddf_batch **out);
+void ddf_batch_destroy(ddf_batch *b);
+int32_t ddf_batch_size(const ddf_batch *b);
+int64_t ddf_batch_step_count(const ddf_batch *b);
+/* Byte offset of instance i's planes in f and g; node offset of its dense fields. */
+int ddf_batch_offsets(const ddf_batch *b, int32_t i, int64_t *pop_offset_bytes, int64_t *field_offset);
+/* Equilibrium initial state of every instance from concatenated FP64 device fields
+ * (same rule as ddf_init_equilibrium); resets the step counter. */
+int ddf_batch_init_equilibrium(ddf_batch *b, const double *rho, const double *ux, const double *uy,
+                               const double *phi, void *stream);
+/* Tiling: tile width at most bx_max (64, 128, 256 or 512; kThreads = 512 threads per
+ * tile) and blocks_per_cu persistent workgroups per compute unit (0 = one workgroup per
+ * tile).  Invalidates the captured graph. */
+int ddf_batch_set_tiling(ddf_batch *b, int32_t bx_max, int32_t blocks_per_cu);
+int ddf_batch_get_tiling(const ddf_batch *b, int32_t *bx_max, int32_t *blocks_per_cu, int32_t *ntiles, int32_t *grid);
+/* Times every (bx_max, blocks_per_cu) candidate for steps_per_trial steps on this
+ * instance mix, applies the fastest and caches it per (storage, instance sizes) for the
+ * process.  The trials overwrite the populations: call it before
+ * ddf_batch_init_equilibrium.  best_ms_per_step is -1 when the cache answered. */
+int ddf_batch_autotune(ddf_batch *b, int32_t steps_per_trial, int32_t *bx_max, int32_t *blocks_per_cu,
+                       float *best_ms_per_step, void *stream);
+/* Steps per captured graph (even; 0 = always launch eagerly). */
+int ddf_batch_set_graph(ddf_batch *b, int32_t steps_per_graph);
+int ddf_batch_step(ddf_batch *b, int64_t nsteps, void *stream);
+/* Per-instance statistics into out[n][DDF_NUM_STATS] (host memory); synchronises.
+ * Returns DDF_ERR_NONFINITE (with out filled) when any instance is non-finite; the
+ * other instances' rows stay valid. */
+int ddf_batch_reduce(ddf_batch *b, double *out, void *stream);
+/* Same as ddf_extract / ddf_get_populations for instance i. */
+int ddf_batch_extract(ddf_batch *b, int32_t i, void *out, uint32_t mask, int32_t out_dtype, void *stream);
+int ddf_batch_get_populations(ddf_batch *b, int32_t i, void *f, void *g, int32_t dtype, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -70,6 +70,23 @@ SIGNATURES = {
     "ddf_set_populations": (C.c_int, [_vp, _vp, _vp, C.c_int32, C.c_int64, _vp]),
     "ddf_step_count": (C.c_int64, [_vp]),
     "ddf_last_error": (C.c_char_p, []),
+    "ddf_batch_population_bytes": (C.c_size_t, [C.c_int32, _P]),
+    "ddf_batch_workspace_bytes": (C.c_size_t, [C.c_int32, _P]),
+    "ddf_batch_create": (C.c_int, [C.c_int32, _P, _vp, _vp, _vp, C.POINTER(_vp)]),
+    "ddf_batch_destroy": (None, [_vp]),
+    "ddf_batch_size": (C.c_int32, [_vp]),
+    "ddf_batch_step_count": (C.c_int64, [_vp]),
+    "ddf_batch_offsets": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "ddf_batch_init_equilibrium": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "ddf_batch_set_tiling": (C.c_int, [_vp, C.c_int32, C.c_int32]),
+    "ddf_batch_get_tiling": (C.c_int, [_vp] + [C.POINTER(C.c_int32)] * 4),
+    "ddf_batch_autotune": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_float), _vp]),
+    "ddf_batch_set_graph": (C.c_int, [_vp, C.c_int32]),
+    "ddf_batch_step": (C.c_int, [_vp, C.c_int64, _vp]),
+    "ddf_batch_reduce": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
+    "ddf_batch_extract": (C.c_int, [_vp, C.c_int32, _vp, C.c_uint32, C.c_int32, _vp]),
+    "ddf_batch_get_populations": (C.c_int, [_vp, C.c_int32, _vp, _vp, C.c_int32, _vp]),
 }
 
 _lib = None

@@ -1,0 +1,147 @@
+"""GPU tests of the batched launch: every instance of a batch matches the FP64 oracle
+and the single-lattice path, graph replays equal eager stepping bit for bit, the
+result does not depend on the tiling, and per-instance statistics flag only the
+instance that holds non-finite values."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from paper_1908_06742_amd import Batch, Lattice
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def mixed_problems(storage):
+    x, y = W.grid(70, 33)
+    yc = (y + 0.5 - 16.5) / 16.5
+    chan = (np.ones_like(x), 0.05 * (1 - yc * yc), 0 * x, 1.0 + (y + 0.5) / 33)
+    return [
+        (W.cavity_problem(40, 200.0, 0.1, storage=storage).with_(ny=27), W.rest_fields(40, 27, 1.0, 0.2)),
+        (W.channel_problem(70, 33, 0.9, 0.57, force=(1e-5, 0.0)).with_(storage=storage, phi0=1.0), chan),
+        (W.cavity_problem(64, 1000.0, 0.08, storage=storage), W.rest_fields(64, 64, 1.0, 0.0)),
+        (W.Problem(nx=100, ny=37, storage=storage, tau=0.6, tau_phi=0.65),
+         W.VortexField(L=100, n_blobs=6, sigma=5.0, u_max=0.04).eval_grid(np.arange(100), np.arange(37))),
+        (W.fourroll_problem(24, 0.01, 0.03).with_(storage=storage), W.fourroll_fields(24, 0.03)),
+    ]
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(np.asarray(b))))
+
+
+@pytest.mark.parametrize("steps", [7, 250])
+def test_batch_fp64_matches_oracle(steps):
+    say(f"case: batch f64 {steps} steps")
+    items = mixed_problems("f64")
+    b = Batch([p for p, _ in items], device=DEV)
+    b.set_graph(100)
+    b.init([f for _, f in items]).step(steps)
+    for i, (pr, fields) in enumerate(items):
+        o = oracle.Oracle(pr, nthreads=8)
+        fo, go, ref = o.run(fields, steps)
+        f, g = (t.cpu().numpy() for t in b.get_populations(i))
+        assert rel(f, fo) < 1e-12 and rel(g, go) < 1e-12, i
+        out = {k: v.cpu().numpy() for k, v in b.extract(i, ["ux", "uy", "phi"]).items()}
+        su = max(np.max(np.abs(ref["ux"])), np.max(np.abs(ref["uy"])))
+        assert np.max(np.abs(out["ux"] - ref["ux"])) < 1e-12 * su, i
+        assert rel(out["phi"], ref["phi"]) < 1e-12, i
+
+
+def test_batch_fp32_equals_single_lattices():
+    # The batch kernel always compiles the wall and force paths (a zero force for the
+    # instances without one), so FMA contraction may differ from the single-lattice
+    # specialisation by an ulp: compare at FP32 round-off.
+    say("case: batch f32 vs single lattices")
+    items = mixed_problems("f32")
+    b = Batch([p for p, _ in items], device=DEV)
+    b.init([f for _, f in items]).step(37)
+    for i, (pr, fields) in enumerate(items):
+        lat = Lattice(pr, device=DEV).init(*fields).step(37)
+        fa, ga = (t.cpu().numpy() for t in b.get_populations(i))
+        fb, gb = (t.cpu().numpy() for t in lat.get_populations())
+        assert rel(fa, fb) < 1e-6 and rel(ga, gb) < 1e-6, i
+
+
+def test_graph_replays_equal_eager_steps():
+    say("case: batch graph replay vs eager")
+    items = mixed_problems("f32")
+    a = Batch([p for p, _ in items], device=DEV)
+    e = Batch([p for p, _ in items], device=DEV)
+    a.set_graph(20)
+    e.set_graph(0)
+    a.init([f for _, f in items])
+    e.init([f for _, f in items])
+    for rep in range(4):
+        a.step(40)       # two graph replays
+        e.step(40)
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 16, device=DEV).sum().item()   # eager work between replays
+        assert math.isfinite(junk)
+        for i in range(len(items)):
+            fa, ga = a.get_populations(i, raw=True)
+            fb, gb = e.get_populations(i, raw=True)
+            assert torch.equal(fa, fb) and torch.equal(ga, gb), (rep, i)
+    assert a.step_count == e.step_count == 160
+
+
+def test_result_independent_of_tiling():
+    say("case: batch tilings")
+    items = mixed_problems("f32")
+    ref = None
+    for bx in (64, 128, 256, 512):
+        for bpc in (0, 2, 8):
+            b = Batch([p for p, _ in items], device=DEV)
+            b.set_tiling(bx, bpc)
+            b.init([f for _, f in items]).step(9)
+            pops = [b.get_populations(i, raw=True) for i in range(len(items))]
+            if ref is None:
+                ref = pops
+            else:
+                for i in range(len(items)):
+                    assert torch.equal(pops[i][0], ref[i][0]) and torch.equal(pops[i][1], ref[i][1]), (bx, bpc, i)
+
+
+def test_autotune_then_run():
+    say("case: batch autotune")
+    items = mixed_problems("f32")
+    b = Batch([p for p, _ in items], device=DEV)
+    t = b.autotune(steps_per_trial=4)
+    assert t["bx_max"] in (64, 128, 256, 512) and t["blocks_per_cu"] in (0, 2, 4, 8) and t["ms_per_step"] > 0
+    b.init([f for _, f in items]).step(10)
+    s = b.reduce()
+    assert np.all(s["nonfinite"] == 0)
+    b2 = Batch([p for p, _ in items], device=DEV)
+    t2 = b2.autotune(steps_per_trial=4)
+    assert (t2["bx_max"], t2["blocks_per_cu"]) == (t["bx_max"], t["blocks_per_cu"]) and t2["ms_per_step"] < 0
+
+
+def test_per_instance_statistics_and_nonfinite_flag():
+    say("case: batch reduce")
+    items = mixed_problems("f64")
+    fields = [list(f) for _, f in items]
+    bad = 3
+    fields[bad][1] = np.array(fields[bad][1], copy=True)
+    fields[bad][1][5, 7] = float("nan")
+    b = Batch([p for p, _ in items], device=DEV)
+    b.init(fields).step(12)
+    s = b.reduce()
+    assert s["nonfinite"][bad] > 0
+    assert all(s["nonfinite"][i] == 0 for i in range(len(items)) if i != bad)
+    for i, (pr, f0) in enumerate(items):
+        if i == bad:
+            continue
+        lat = Lattice(pr, device=DEV).init(*fields[i]).step(12)
+        m = lat.reduce()
+        assert abs(m["mass"] - s["mass"][i]) <= 1e-12 * abs(m["mass"]), i
+        assert abs(m["scalar"] - s["scalar"][i]) <= 1e-12 * abs(m["scalar"]) + 1e-12, i
