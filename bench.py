@@ -25,7 +25,8 @@ HBM_PEAK_GBS = 8000.0
 LB_STEPS_PER_STEP = 100
 BYTES_PER_NODE = {"f64": 288, "f32": 144, "f16": 72, "bf16": 72}
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_vortex8192_f32_counters.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1908_06742_amd", "csrc", n) for n in ("ddf.hip", "ddf_device.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1908_06742_amd", "csrc", n)
+                  for n in ("ddf.hip", "ddf_kernels.hpp", "ddf_device.hpp")]
 
 
 def kernel_hash():
@@ -64,6 +65,8 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP):
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
 
+    last = {}
+
     def one(kernel_events=None):
         if kernel_events is not None:
             e0 = torch.cuda.Event(enable_timing=True)
@@ -73,7 +76,7 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP):
         if kernel_events is not None:
             e1.record(stream)
             kernel_events.append((e0, e1))
-        lat.reduce()       # synchronises the stream
+        last.update(lat.reduce())       # synchronises the stream
         lat.extract(names, out=out)
 
     for _ in range(warmup):
@@ -86,7 +89,7 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kern_ms = sum(a.elapsed_time(b) for a, b in evs) / (steps * lb_steps)
-    stats = lat.reduce()
+    stats = dict(last)
     nodes = L * L
     return {
         "nodes": nodes,

@@ -24,18 +24,40 @@ def hipcc():
             return c
 
 
+def _filter(text):
+    return "\n".join(l for l in text.splitlines() if "packed-fp32-ops" not in l)
+
+
 def build(verbose: bool = True) -> str:
-    """Compile every HIP source into libddf.so (always rebuilds)."""
+    """Compile every HIP source (in parallel) and link libddf.so (always rebuilds)."""
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(HERE, "csrc", os.path.basename(src) + ".o")
+        cmd = [hipcc()] + HIPCC_FLAGS[:] + ["-c", "-o", obj, src]
+        cmd.remove("-shared")
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True))
+        objs.append(obj)
+    failed = False
+    for pr in procs:
+        out, _ = pr.communicate()
+        if pr.returncode != 0:
+            sys.stderr.write(_filter(out) + "\n")
+            failed = True
+    if failed:
+        raise RuntimeError("hipcc failed compiling libddf sources")
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-o", tmp] + SOURCES
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
-    out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
-        sys.stderr.write(out + "\n")
-        raise RuntimeError("hipcc failed building libddf.so")
+        sys.stderr.write(_filter(r.stdout + r.stderr) + "\n")
+        raise RuntimeError("hipcc failed linking libddf.so")
     os.replace(tmp, LIB)
+    for o in objs:
+        os.remove(o)
     return LIB
 
 
