@@ -200,6 +200,14 @@ int ddf_batch_get_tiling(const ddf_batch *b, int32_t *bx_max, int32_t *blocks_pe
  * ddf_batch_init_equilibrium.  best_ms_per_step is -1 when the cache answered. */
 int ddf_batch_autotune(ddf_batch *b, int32_t steps_per_trial, int32_t *bx_max, int32_t *blocks_per_cu,
                        float *best_ms_per_step, void *stream);
+/* active[i] != 0 keeps instance i in the step list (all instances start active); inactive
+ * instances keep their state and still appear in reductions.  Rebuilds the list and
+ * invalidates the captured graph. */
+int ddf_batch_set_active(ddf_batch *b, const uint8_t *active);
+/* Re-initialise instance i alone at equilibrium from dense FP64 device fields of its
+ * size (same rule as ddf_init_equilibrium); the batch step count must be even. */
+int ddf_batch_init_instance(ddf_batch *b, int32_t i, const double *rho, const double *ux, const double *uy,
+                            const double *phi, void *stream);
 /* Steps per captured graph (even; 0 = always launch eagerly). */
 int ddf_batch_set_graph(ddf_batch *b, int32_t steps_per_graph);
 int ddf_batch_step(ddf_batch *b, int64_t nsteps, void *stream);

@@ -83,11 +83,39 @@ SIGNATURES = {
     "ddf_batch_autotune": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_float), _vp]),
     "ddf_batch_set_graph": (C.c_int, [_vp, C.c_int32]),
+    "ddf_batch_set_active": (C.c_int, [_vp, C.POINTER(C.c_uint8)]),
+    "ddf_batch_init_instance": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp]),
     "ddf_batch_step": (C.c_int, [_vp, C.c_int64, _vp]),
     "ddf_batch_reduce": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
     "ddf_batch_extract": (C.c_int, [_vp, C.c_int32, _vp, C.c_uint32, C.c_int32, _vp]),
     "ddf_batch_get_populations": (C.c_int, [_vp, C.c_int32, _vp, _vp, C.c_int32, _vp]),
 }
+
+# Surrogate-network kernels (include/ddf_nn.h).
+_i32, _i64, _f32 = C.c_int32, C.c_int64, C.c_float
+_fp = C.POINTER(C.c_float)
+_dp = C.POINTER(C.c_double)
+NN_SIGNATURES = {
+    "ddf_nn_conv3x3": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32,
+                                 _vp]),
+    "ddf_nn_wgrad_workspace_bytes": (C.c_size_t, [_i32, _i32, _i32, _i32, _i32, C.POINTER(_i32)]),
+    "ddf_nn_conv3x3_wgrad": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _i32, _vp, _vp, _i32,
+                                       _vp, _vp]),
+    "ddf_nn_relu_bwd": (C.c_int, [_vp, _vp, _i64, _vp]),
+    "ddf_nn_pool2": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp]),
+    "ddf_nn_pool2_bwd": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _i32, _vp]),
+    "ddf_nn_up2": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _i32, _i32, _vp]),
+    "ddf_nn_up2_bwd": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp]),
+    "ddf_nn_slice": (C.c_int, [_vp, _i32, _i32, _vp, _i32, _i32, _i64, _i32, _i32, _vp]),
+    "ddf_nn_mse_workspace_bytes": (C.c_size_t, [_i64]),
+    "ddf_nn_mse": (C.c_int, [_vp, _i32, _vp, _i64, _fp, _vp, _vp, _vp, _vp]),
+    "ddf_nn_adam": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _i64, _f32, _vp]),
+    "ddf_nn_cast_weights": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp]),
+    "ddf_nn_cavity_inputs": (C.c_int, [_vp, _vp, _i32, _i32, _i32, _i32, _f32, _f32, _f32, _vp, _vp]),
+    "ddf_nn_cavity_targets": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp]),
+    "ddf_nn_cavity_fields": (C.c_int, [_vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
+}
+SIGNATURES.update(NN_SIGNATURES)
 
 _lib = None
 

@@ -59,6 +59,25 @@ class Batch:
         self._keep = cat
         return self
 
+    def init_device(self, rho, ux, uy, phi):
+        """Initialise from concatenated FP64 device tensors (instance order, [ny][nx] each)."""
+        fields = [t.to(self.device, torch.float64).contiguous().reshape(-1) for t in (rho, ux, uy, phi)]
+        L.check(L.lib().ddf_batch_init_equilibrium(self._h, *[_ptr(t) for t in fields], _stream_ptr(self.stream)))
+        self._keep = fields
+        return self
+
+    def init_instance(self, i, rho, ux, uy, phi):
+        p = self.problems[i]
+        fields = [torch.as_tensor(np.broadcast_to(np.asarray(a, np.float64), (p.ny, p.nx)) if not torch.is_tensor(a)
+                                  else a).to(self.device, torch.float64).contiguous() for a in (rho, ux, uy, phi)]
+        L.check(L.lib().ddf_batch_init_instance(self._h, int(i), *[_ptr(t) for t in fields], _stream_ptr(self.stream)))
+        self._keep_i = fields
+        return self
+
+    def set_active(self, active):
+        a = (C.c_uint8 * self.n)(*[1 if x else 0 for x in active])
+        L.check(L.lib().ddf_batch_set_active(self._h, a))
+
     def autotune(self, steps_per_trial=20):
         bx, bpc, ms = C.c_int32(), C.c_int32(), C.c_float()
         L.check(L.lib().ddf_batch_autotune(self._h, int(steps_per_trial), C.byref(bx), C.byref(bpc), C.byref(ms),

@@ -111,11 +111,14 @@ struct ddf_batch {
     void *f, *g, *ws;
     // workspace carve-up
     void *d_inst;
-    TileRef *d_tiles;
+    TileRef *d_tiles;        // all tiles (reductions)
+    TileRef *d_step_tiles;   // tiles of the active instances (stepping)
+    int nstep_tiles;
     int *d_first, *d_count;
     double *d_partials, *d_out;
     void *d_snap;
     int max_tiles;
+    std::vector<unsigned char> active;   // instances whose tiles are in the step list
     // tiling
     int bx_max, bpc, ntiles, grid;
     std::vector<int> first, count;
@@ -149,7 +152,7 @@ Carve carve(int n, const ddf_params *ps, int max_tiles, int64_t total_nodes)
     Carve c;
     size_t o = 0;
     c.inst = o; o += align256((size_t)n * inst_desc_size(ps[0].storage));
-    c.tiles = o; o += align256((size_t)max_tiles * sizeof(TileRef));
+    c.tiles = o; o += 2 * align256((size_t)max_tiles * sizeof(TileRef));
     c.first = o; o += align256((size_t)n * sizeof(int));
     c.count = o; o += align256((size_t)n * sizeof(int));
     c.partials = o; o += align256((size_t)max_tiles * RS_N * sizeof(double));
@@ -239,11 +242,17 @@ int apply_tiling(ddf_batch *b, int bx_max, int bpc, hipStream_t st)
         b->count[tl[k].inst]++;
     }
     DDF_HIP_TRY(hipMemcpyAsync(b->d_inst, blob.data(), blob.size(), hipMemcpyHostToDevice, st));
+    std::vector<TileRef> act;
+    for (const TileRef &t : tl)
+        if (b->active[t.inst]) act.push_back(t);
+    b->nstep_tiles = (int)act.size();
     DDF_HIP_TRY(hipMemcpyAsync(b->d_tiles, tl.data(), tl.size() * sizeof(TileRef), hipMemcpyHostToDevice, st));
+    if (!act.empty())
+        DDF_HIP_TRY(hipMemcpyAsync(b->d_step_tiles, act.data(), act.size() * sizeof(TileRef), hipMemcpyHostToDevice, st));
     DDF_HIP_TRY(hipMemcpyAsync(b->d_first, b->first.data(), b->n * sizeof(int), hipMemcpyHostToDevice, st));
     DDF_HIP_TRY(hipMemcpyAsync(b->d_count, b->count.data(), b->n * sizeof(int), hipMemcpyHostToDevice, st));
     DDF_HIP_TRY(hipStreamSynchronize(st));   // host vectors are released on return
-    const int g = bpc == 0 ? b->ntiles : bpc * b->num_cu;
+    const int g = bpc == 0 ? b->nstep_tiles : bpc * b->num_cu;
     b->grid = std::max(8, (g + 7) / 8 * 8);
     drop_graph(b);
     return DDF_OK;
@@ -254,12 +263,13 @@ void launch_batch_step(ddf_batch *b, hipStream_t st, bool odd, int64_t t)
 {
     using R = typename Codec<S>::R;
     const auto *inst = (const InstDesc<R> *)b->d_inst;
+    if (b->nstep_tiles == 0) return;
     if (odd)
         hipLaunchKernelGGL((k_batch_step<S, SC, true>), dim3(b->grid), dim3(kThreads), 0, st, (S *)b->f, (S *)b->g,
-                           inst, b->d_tiles, b->ntiles, t);
+                           inst, b->d_step_tiles, b->nstep_tiles, t);
     else
         hipLaunchKernelGGL((k_batch_step<S, SC, false>), dim3(b->grid), dim3(kThreads), 0, st, (S *)b->f, (S *)b->g,
-                           inst, b->d_tiles, b->ntiles, t);
+                           inst, b->d_step_tiles, b->nstep_tiles, t);
 }
 
 void launch_one_step(ddf_batch *b, hipStream_t st, int64_t step)
@@ -348,6 +358,8 @@ int ddf_batch_create(int32_t n, const ddf_params *ps, void *pop_f, void *pop_g, 
     char *w = (char *)workspace;
     b->d_inst = w + c.inst;
     b->d_tiles = (TileRef *)(w + c.tiles);
+    b->d_step_tiles = (TileRef *)(w + c.tiles + align256((size_t)b->max_tiles * sizeof(TileRef)));
+    b->active.assign(n, 1);
     b->d_first = (int *)(w + c.first);
     b->d_count = (int *)(w + c.count);
     b->d_partials = (double *)(w + c.partials);
@@ -421,6 +433,34 @@ int ddf_batch_init_equilibrium(ddf_batch *b, const double *rho, const double *ux
     b->step = 0;
     b->snap_valid = false;
     b->initialised = true;
+    return DDF_OK;
+}
+
+int ddf_batch_set_active(ddf_batch *b, const uint8_t *active)
+{
+    if (!b) return fail(DDF_ERR_ARG, "batch is NULL");
+    if (!active) return fail(DDF_ERR_ARG, "active is NULL");
+    for (int i = 0; i < b->n; ++i) b->active[i] = active[i] ? 1 : 0;
+    return apply_tiling(b, b->bx_max, b->bpc, b->cap_stream);
+}
+
+int ddf_batch_init_instance(ddf_batch *b, int32_t i, const double *rho, const double *ux, const double *uy,
+                            const double *phi, void *stream)
+{
+    if (!b || i < 0 || i >= b->n) return fail(DDF_ERR_ARG, "bad batch or instance index");
+    if (!rho || !ux || !uy || !phi) return fail(DDF_ERR_ARG, "a field pointer is NULL");
+    if (!b->initialised) return fail(DDF_ERR_STATE, "init_instance before ddf_batch_init_equilibrium");
+    if (b->step & 1) return fail(DDF_ERR_STATE, "init_instance needs an even step count (natural slot order)");
+    const size_t s = storage_size(b->storage);
+    const Geom G = make_geom(b->p[i]);
+    with_storage(b->storage, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL((k_init<S>), dim3(grid_blocks(G)), dim3(kThreads), 0, (hipStream_t)stream,
+                           (S *)((char *)b->f + b->off[i] * s), (S *)((char *)b->g + b->off[i] * s), G,
+                           b->P[i].of<S>(), rho, ux, uy, phi);
+        return 0;
+    });
+    DDF_HIP_TRY(hipGetLastError());
     return DDF_OK;
 }
 

@@ -1,0 +1,524 @@
+// libddf, surrogate network kernels: the building blocks of a 2D U-Net on NHWC BF16
+// activations with FP32 accumulation on the gfx950 matrix cores, its backward pass and
+// an Adam step on FP32 master weights.  Declared in include/ddf_nn.h.
+//
+// 3x3 convolutions are implicit GEMMs: rows = output pixels, columns = output
+// channels, reduction = 9 taps x input channels.  One wavefront owns a 32 x 32 output
+// tile and issues v_mfma_f32_32x32x16_bf16 (A: 32 pixels x 16 channels of one tap,
+// B: 16 channels x 32 output channels); lane l holds A[l % 32][8 (l / 32) + i] and
+// B[8 (l / 32) + i][l % 32], i < 8, and receives C[8 (j / 4) + 4 (l / 32) + j % 4][l % 32],
+// j < 16.  The data gradient is the same kernel on the output gradient with the taps
+// flipped and the weight transposed; the weight gradient is a split-K GEMM over pixels
+// whose FP32 partials are summed in a fixed order (deterministic).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <algorithm>
+#include <string>
+
+#include "../../include/ddf_nn.h"
+#include "ddf_kernels.hpp"
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+using ddf::host::fail;
+
+__device__ __forceinline__ bf16x8 load8(const __bf16 *p) { return *(const bf16x8 *)p; }
+
+__device__ __forceinline__ bf16x8 zero8()
+{
+    bf16x8 z;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) z[i] = (__bf16)0.0f;
+    return z;
+}
+
+// out[p, oc0 + co] (= or +=) act(bias[co] + sum_{tap, ci} in[p + d(tap), ic0 + ci] w[tap][co][ci])
+// WM x WN waves per workgroup, each a 32 x 32 tile.  Requirements (checked on the host):
+// Cin % 16 == 0, Cout % (32 WN) == 0, npix % (32 WM) == 0, channel strides and offsets
+// multiples of 8.
+template <int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_conv3x3(const __bf16 *__restrict__ in, int N, int H, int W, int Cin,
+                                                          int in_cs, int in_co, const __bf16 *__restrict__ wt,
+                                                          const float *__restrict__ bias, __bf16 *__restrict__ out,
+                                                          int Cout, int out_cs, int out_co, int relu, int accumulate)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int p0 = (blockIdx.x * WM + wm) * 32;
+    const int co0 = (blockIdx.y * WN + wn) * 32;
+    const int m = lane & 31, half = lane >> 5;
+    // pixel of this lane's A row
+    const int p = p0 + m;
+    const int n = p / (H * W), rem = p - n * (H * W);
+    const int y = rem / W, x = rem - y * W;
+    f32x16 acc = {};
+    const __bf16 *wrow = wt + (int64_t)(co0 + m) * Cin + 8 * half;
+    for (int tap = 0; tap < 9; ++tap) {
+        const int iy = y + tap / 3 - 1, ix = x + tap % 3 - 1;
+        const bool ok = iy >= 0 && iy < H && ix >= 0 && ix < W;
+        const int64_t aoff = ok ? ((int64_t)(n * H + iy) * W + ix) * in_cs + in_co + 8 * half : 0;
+        const __bf16 *arow = in + aoff;
+        const __bf16 *brow = wrow + (int64_t)tap * Cout * Cin;
+        for (int c0 = 0; c0 < Cin; c0 += 16) {
+            const bf16x8 a = ok ? load8(arow + c0) : zero8();
+            const bf16x8 b = load8(brow + c0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+    }
+    const int co = co0 + m;
+    const float bv = bias ? bias[co] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int pr = p0 + 8 * (j >> 2) + 4 * half + (j & 3);
+        __bf16 *o = out + (int64_t)pr * out_cs + out_co + co;
+        float v = acc[j] + bv;
+        if (relu) v = fmaxf(v, 0.0f);
+        if (accumulate) v += (float)*o;
+        *o = (__bf16)v;
+    }
+}
+
+// Split-K weight gradient: part[chunk][tap][co][ci] = sum over the chunk's pixels p of
+// dout[p, co] * in[p + d(tap), ci].  One wavefront per (ci tile, co tile, tap, chunk).
+__global__ __launch_bounds__(64) void k_conv3x3_wgrad(const __bf16 *__restrict__ in, int N, int H, int W, int Cin,
+                                                      int in_cs, int in_co, const __bf16 *__restrict__ dout, int Cout,
+                                                      int d_cs, int chunk, float *__restrict__ part)
+{
+    const int lane = threadIdx.x, m = lane & 31, half = lane >> 5;
+    const int tiles_ci = Cin / 32;
+    const int ci0 = (blockIdx.x % tiles_ci) * 32, co0 = (blockIdx.x / tiles_ci) * 32;
+    const int tap = blockIdx.y, ck = blockIdx.z;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int npix = N * H * W;
+    const int pbeg = ck * chunk, pend = min(npix, pbeg + chunk);
+    f32x16 acc = {};
+    for (int k0 = pbeg; k0 < pend; k0 += 16) {
+        bf16x8 a, b;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int pk = k0 + 8 * half + i;
+            const bool inr = pk < pend;
+            // A[m = co][k = pixel]
+            a[i] = inr ? dout[(int64_t)pk * d_cs + co0 + m] : (__bf16)0.0f;
+            // B[k = pixel][n = ci]: input at the shifted pixel (zero outside)
+            __bf16 bv = (__bf16)0.0f;
+            if (inr) {
+                const int n = pk / (H * W), rem = pk - n * (H * W);
+                const int y = rem / W + dy, x = rem % W + dx;
+                if (y >= 0 && y < H && x >= 0 && x < W)
+                    bv = in[((int64_t)(n * H + y) * W + x) * in_cs + in_co + ci0 + m];
+            }
+            b[i] = bv;
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    float *o = part + (((int64_t)ck * 9 + tap) * Cout) * Cin;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int co = co0 + 8 * (j >> 2) + 4 * half + (j & 3);
+        o[(int64_t)co * Cin + ci0 + m] = acc[j];
+    }
+}
+
+// out[i] (= or +=) sum_c part[c][i], c = 0 .. nchunk-1 in order.
+__global__ void k_sum_chunks(const float *__restrict__ part, int64_t n, int nchunk, float *__restrict__ out, int accumulate)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * n + i];
+    out[i] = accumulate ? out[i] + s : s;
+}
+
+// Bias gradient partials: part[b][co] = sum of dout[p, co] over pixel block b (256 pixels).
+__global__ __launch_bounds__(256) void k_bias_grad(const __bf16 *__restrict__ dout, int npix, int Cout, int d_cs,
+                                                   float *__restrict__ part)
+{
+    const int co = threadIdx.x;
+    if (co >= Cout) return;
+    const int p0 = blockIdx.x * 256, p1 = min(npix, p0 + 256);
+    float s = 0.0f;
+    for (int p = p0; p < p1; ++p) s += (float)dout[(int64_t)p * d_cs + co];
+    part[(int64_t)blockIdx.x * Cout + co] = s;
+}
+
+__global__ void k_relu_bwd(__bf16 *__restrict__ g, const __bf16 *__restrict__ act, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !((float)act[i] > 0.0f)) g[i] = (__bf16)0.0f;
+}
+
+// 2x2 average pooling and its adjoint (NHWC, C channels, contiguous).
+__global__ void k_pool2(const __bf16 *__restrict__ in, int N, int H, int W, int C, __bf16 *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int h = H / 2, w = W / 2;
+    if (i >= (int64_t)N * h * w * C) return;
+    const int c = i % C;
+    const int64_t q = i / C;
+    const int xo = q % w, yo = (q / w) % h, n = q / ((int64_t)w * h);
+    const __bf16 *b = in + ((int64_t)(n * H + 2 * yo) * W + 2 * xo) * C + c;
+    const float s = (float)b[0] + (float)b[C] + (float)b[(int64_t)W * C] + (float)b[(int64_t)W * C + C];
+    out[i] = (__bf16)(0.25f * s);
+}
+
+__global__ void k_pool2_bwd(const __bf16 *__restrict__ dout, int N, int H, int W, int C, __bf16 *__restrict__ din,
+                            int accumulate)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * H * W * C) return;
+    const int c = i % C;
+    const int64_t q = i / C;
+    const int x = q % W, y = (q / W) % H, n = q / ((int64_t)W * H);
+    const float v = 0.25f * (float)dout[((int64_t)(n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
+    din[i] = (__bf16)(accumulate ? (float)din[i] + v : v);
+}
+
+// Nearest-neighbour 2x upsampling of in (h x w) into channels [oc0, oc0 + C) of out
+// (2h x 2w, channel stride out_cs), and the adjoint.
+__global__ void k_up2(const __bf16 *__restrict__ in, int N, int h, int w, int C, __bf16 *__restrict__ out, int out_cs,
+                      int oc0)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int H = 2 * h, W = 2 * w;
+    if (i >= (int64_t)N * H * W * C) return;
+    const int c = i % C;
+    const int64_t q = i / C;
+    const int x = q % W, y = (q / W) % H, n = q / ((int64_t)W * H);
+    out[q * out_cs + oc0 + c] = in[((int64_t)(n * h + y / 2) * w + x / 2) * C + c];
+}
+
+__global__ void k_up2_bwd(const __bf16 *__restrict__ dout, int N, int h, int w, int C, int d_cs, int dc0,
+                          __bf16 *__restrict__ din)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * h * w * C) return;
+    const int c = i % C;
+    const int64_t q = i / C;
+    const int x = q % w, y = (q / w) % h, n = q / ((int64_t)w * h);
+    const int W = 2 * w;
+    const int64_t b = ((int64_t)(n * 2 * h + 2 * y) * W + 2 * x);
+    const float s = (float)dout[b * d_cs + dc0 + c] + (float)dout[(b + 1) * d_cs + dc0 + c] +
+                    (float)dout[(b + W) * d_cs + dc0 + c] + (float)dout[(b + W + 1) * d_cs + dc0 + c];
+    din[i] = (__bf16)s;
+}
+
+// dst[p, dc0 + c] (= or +=) src[p, sc0 + c], c < C: channel-slice copy (concatenation and its adjoint).
+__global__ void k_slice(const __bf16 *__restrict__ src, int s_cs, int sc0, __bf16 *__restrict__ dst, int d_cs, int dc0,
+                        int64_t npix, int C, int accumulate)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix * C) return;
+    const int c = i % C;
+    const int64_t p = i / C;
+    const float v = (float)src[p * s_cs + sc0 + c];
+    __bf16 *d = dst + p * d_cs + dc0 + c;
+    *d = (__bf16)(accumulate ? (float)*d + v : v);
+}
+
+// Weighted MSE over the first 4 channels of out (channel stride o_cs): per-block FP64
+// partial of sum_c w_c (out_c - t_c)^2, and d out = 2 w_c (out_c - t_c) / npix (zero in
+// the padding channels).
+__global__ __launch_bounds__(256) void k_mse(const __bf16 *__restrict__ out, int o_cs, const float *__restrict__ target,
+                                             int64_t npix, float w0, float w1, float w2, float w3,
+                                             __bf16 *__restrict__ dout, double *__restrict__ part)
+{
+    __shared__ double sh[256];
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double acc = 0.0;
+    if (p < npix) {
+        const float wc[4] = {w0, w1, w2, w3};
+        for (int c = 0; c < o_cs; ++c) {
+            float g = 0.0f;
+            if (c < 4) {
+                const float d = (float)out[p * o_cs + c] - target[p * 4 + c];
+                acc += (double)wc[c] * (double)d * (double)d;
+                g = 2.0f * wc[c] * d / (float)npix;
+            }
+            dout[p * o_cs + c] = (__bf16)g;
+        }
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_f64(const double *__restrict__ part, int n, double *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    out[0] = s;
+}
+
+// Adam with bias correction on FP32 master weights.
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+                       int64_t n, float lr, float b1, float b2, float eps, float c1, float c2, float wd)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i] + wd * w[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// FP32 master weight w[9][Cout][Cin] -> BF16 forward copy wf[9][Cout_p][Cin_p] and the
+// tap-flipped transpose for the data gradient wd[9][Cin_p][Cout_p] (zero padding).
+__global__ void k_cast_weights(const float *__restrict__ w, int Cout, int Cin, int Cout_p, int Cin_p,
+                               __bf16 *__restrict__ wf, __bf16 *__restrict__ wd)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)9 * Cout_p * Cin_p) return;
+    const int ci = i % Cin_p;
+    const int co = (i / Cin_p) % Cout_p;
+    const int tap = i / ((int64_t)Cin_p * Cout_p);
+    const float v = (co < Cout && ci < Cin) ? w[((int64_t)tap * Cout + co) * Cin + ci] : 0.0f;
+    wf[i] = (__bf16)v;
+    if (wd) wd[((int64_t)(8 - tap) * Cin_p + ci) * Cout_p + co] = (__bf16)v;
+}
+
+// Network input for lid-driven cavities: channel 0 wall mask (1 next to a fixed wall,
+// 2 next to the lid), channel 1 (log Re - log Re_lo) / (log Re_hi - log Re_lo), channel
+// 2 U / U_ref, channels 3..C-1 zero.  re, u: per-sample values.
+__global__ void k_cavity_inputs(const float *__restrict__ re, const float *__restrict__ u, int N, int H, int W, int C,
+                                float lre_lo, float lre_hi, float u_ref, __bf16 *__restrict__ x)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * H * W) return;
+    const int px = i % W, py = (i / W) % H, n = i / ((int64_t)W * H);
+    float mask = (px == 0 || px == W - 1 || py == 0) ? 1.0f : 0.0f;
+    if (py == H - 1) mask = 2.0f;
+    __bf16 *o = x + i * C;
+    o[0] = (__bf16)mask;
+    o[1] = (__bf16)((logf(re[n]) - lre_lo) / (lre_hi - lre_lo));
+    o[2] = (__bf16)(u[n] / u_ref);
+    for (int c = 3; c < C; ++c) o[c] = (__bf16)0.0f;
+}
+
+// Normalised training targets from steady fields (dense FP64 [N][H][W] each):
+// (u / U, v / U, (rho - 1) / U^2, phi).
+__global__ void k_cavity_targets(const double *__restrict__ rho, const double *__restrict__ ux,
+                                 const double *__restrict__ uy, const double *__restrict__ phi,
+                                 const float *__restrict__ u, int N, int HW, float *__restrict__ t)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * HW) return;
+    const float U = u[i / HW];
+    t[i * 4 + 0] = (float)(ux[i] / U);
+    t[i * 4 + 1] = (float)(uy[i] / U);
+    t[i * 4 + 2] = (float)((rho[i] - 1.0) / ((double)U * U));
+    t[i * 4 + 3] = (float)phi[i];
+}
+
+// Network output (channel stride o_cs) -> physical FP64 fields for a warm start.
+__global__ void k_cavity_fields(const __bf16 *__restrict__ out, int o_cs, const float *__restrict__ u, int N, int HW,
+                                double *__restrict__ rho, double *__restrict__ ux, double *__restrict__ uy,
+                                double *__restrict__ phi)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * HW) return;
+    const double U = u[i / HW];
+    const __bf16 *o = out + i * o_cs;
+    ux[i] = U * (double)(float)o[0];
+    uy[i] = U * (double)(float)o[1];
+    rho[i] = 1.0 + U * U * (double)(float)o[2];
+    phi[i] = (double)(float)o[3];
+}
+
+inline int blocks_for(int64_t n, int t = 256) { return (int)((n + t - 1) / t); }
+
+int check_launch()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DDF_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return DDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ddf_nn_conv3x3(const void *in, int32_t N, int32_t H, int32_t W, int32_t Cin, int32_t in_cs, int32_t in_co,
+                   const void *wt, const float *bias, void *out, int32_t Cout, int32_t out_cs, int32_t out_co,
+                   int32_t relu, int32_t accumulate, void *stream)
+{
+    const int64_t npix = (int64_t)N * H * W;
+    if (!in || !wt || !out || N <= 0 || H <= 0 || W <= 0) return fail(DDF_ERR_ARG, "conv3x3: bad tensor arguments");
+    if (Cin % 16 || Cout % 32 || in_cs % 8 || in_co % 8 || out_cs < out_co + Cout || in_cs < in_co + Cin)
+        return fail(DDF_ERR_ARG, "conv3x3: need Cin % 16 == 0, Cout % 32 == 0, 8-aligned channel strides and offsets");
+    if (npix % 32) return fail(DDF_ERR_ARG, "conv3x3: N*H*W must be a multiple of 32");
+    if (npix > (int64_t)1 << 30) return fail(DDF_ERR_ARG, "conv3x3: too many pixels");
+    hipStream_t st = (hipStream_t)stream;
+    const __bf16 *i = (const __bf16 *)in;
+    const __bf16 *w = (const __bf16 *)wt;
+    __bf16 *o = (__bf16 *)out;
+    if (Cout % 64 == 0 && npix % 64 == 0)
+        hipLaunchKernelGGL((k_conv3x3<2, 2>), dim3(npix / 64, Cout / 64), dim3(256), 0, st, i, N, H, W, Cin, in_cs,
+                           in_co, w, bias, o, Cout, out_cs, out_co, relu, accumulate);
+    else if (npix % 128 == 0)
+        hipLaunchKernelGGL((k_conv3x3<4, 1>), dim3(npix / 128, Cout / 32), dim3(256), 0, st, i, N, H, W, Cin, in_cs,
+                           in_co, w, bias, o, Cout, out_cs, out_co, relu, accumulate);
+    else
+        hipLaunchKernelGGL((k_conv3x3<1, 1>), dim3(npix / 32, Cout / 32), dim3(64), 0, st, i, N, H, W, Cin, in_cs,
+                           in_co, w, bias, o, Cout, out_cs, out_co, relu, accumulate);
+    return check_launch();
+}
+
+size_t ddf_nn_wgrad_workspace_bytes(int32_t N, int32_t H, int32_t W, int32_t Cin, int32_t Cout, int32_t *chunk_out)
+{
+    const int64_t npix = (int64_t)N * H * W;
+    // chunk: at least 512 pixels, at most 64 chunks
+    int64_t chunk = std::max<int64_t>(512, (npix + 63) / 64);
+    chunk = (chunk + 15) / 16 * 16;
+    const int64_t nchunk = (npix + chunk - 1) / chunk;
+    if (chunk_out) *chunk_out = (int32_t)chunk;
+    const int64_t wsz = (int64_t)9 * Cout * Cin;
+    const int64_t bsz = ((npix + 255) / 256) * Cout;
+    return (size_t)std::max(nchunk * wsz, bsz) * sizeof(float);
+}
+
+int ddf_nn_conv3x3_wgrad(const void *in, int32_t N, int32_t H, int32_t W, int32_t Cin, int32_t in_cs, int32_t in_co,
+                         const void *dout, int32_t Cout, int32_t d_cs, float *dw, float *db, int32_t accumulate,
+                         void *workspace, void *stream)
+{
+    if (!in || !dout || !dw || !workspace) return fail(DDF_ERR_ARG, "wgrad: null pointer");
+    if (Cin % 32 || Cout % 32) return fail(DDF_ERR_ARG, "wgrad: Cin and Cout must be multiples of 32");
+    hipStream_t st = (hipStream_t)stream;
+    int32_t chunk;
+    ddf_nn_wgrad_workspace_bytes(N, H, W, Cin, Cout, &chunk);
+    const int64_t npix = (int64_t)N * H * W;
+    const int nchunk = (int)((npix + chunk - 1) / chunk);
+    float *part = (float *)workspace;
+    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3((Cin / 32) * (Cout / 32), 9, nchunk), dim3(64), 0, st,
+                       (const __bf16 *)in, N, H, W, Cin, in_cs, in_co, (const __bf16 *)dout, Cout, d_cs, chunk, part);
+    const int64_t wsz = (int64_t)9 * Cout * Cin;
+    hipLaunchKernelGGL(k_sum_chunks, dim3(blocks_for(wsz)), dim3(256), 0, st, part, wsz, nchunk, dw, accumulate);
+    if (db) {
+        const int nb = (int)((npix + 255) / 256);
+        hipLaunchKernelGGL(k_bias_grad, dim3(nb), dim3(256), 0, st, (const __bf16 *)dout, (int)npix, Cout, d_cs, part);
+        hipLaunchKernelGGL(k_sum_chunks, dim3(blocks_for(Cout)), dim3(256), 0, st, part, (int64_t)Cout, nb, db, accumulate);
+    }
+    return check_launch();
+}
+
+int ddf_nn_relu_bwd(void *grad, const void *act, int64_t n, void *stream)
+{
+    if (!grad || !act) return fail(DDF_ERR_ARG, "relu_bwd: null pointer");
+    hipLaunchKernelGGL(k_relu_bwd, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, (__bf16 *)grad,
+                       (const __bf16 *)act, n);
+    return check_launch();
+}
+
+int ddf_nn_pool2(const void *in, int32_t N, int32_t H, int32_t W, int32_t C, void *out, void *stream)
+{
+    if (H % 2 || W % 2) return fail(DDF_ERR_ARG, "pool2: H and W must be even");
+    hipLaunchKernelGGL(k_pool2, dim3(blocks_for((int64_t)N * H * W * C / 4)), dim3(256), 0, (hipStream_t)stream,
+                       (const __bf16 *)in, N, H, W, C, (__bf16 *)out);
+    return check_launch();
+}
+
+int ddf_nn_pool2_bwd(const void *dout, int32_t N, int32_t H, int32_t W, int32_t C, void *din, int32_t accumulate,
+                     void *stream)
+{
+    if (H % 2 || W % 2) return fail(DDF_ERR_ARG, "pool2_bwd: H and W must be even");
+    hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks_for((int64_t)N * H * W * C)), dim3(256), 0, (hipStream_t)stream,
+                       (const __bf16 *)dout, N, H, W, C, (__bf16 *)din, accumulate);
+    return check_launch();
+}
+
+int ddf_nn_up2(const void *in, int32_t N, int32_t h, int32_t w, int32_t C, void *out, int32_t out_cs, int32_t out_co,
+               void *stream)
+{
+    hipLaunchKernelGGL(k_up2, dim3(blocks_for((int64_t)N * 4 * h * w * C)), dim3(256), 0, (hipStream_t)stream,
+                       (const __bf16 *)in, N, h, w, C, (__bf16 *)out, out_cs, out_co);
+    return check_launch();
+}
+
+int ddf_nn_up2_bwd(const void *dout, int32_t N, int32_t h, int32_t w, int32_t C, int32_t d_cs, int32_t d_co, void *din,
+                   void *stream)
+{
+    hipLaunchKernelGGL(k_up2_bwd, dim3(blocks_for((int64_t)N * h * w * C)), dim3(256), 0, (hipStream_t)stream,
+                       (const __bf16 *)dout, N, h, w, C, d_cs, d_co, (__bf16 *)din);
+    return check_launch();
+}
+
+int ddf_nn_slice(const void *src, int32_t s_cs, int32_t s_co, void *dst, int32_t d_cs, int32_t d_co, int64_t npix,
+                 int32_t C, int32_t accumulate, void *stream)
+{
+    hipLaunchKernelGGL(k_slice, dim3(blocks_for(npix * C)), dim3(256), 0, (hipStream_t)stream, (const __bf16 *)src, s_cs,
+                       s_co, (__bf16 *)dst, d_cs, d_co, npix, C, accumulate);
+    return check_launch();
+}
+
+size_t ddf_nn_mse_workspace_bytes(int64_t npix) { return (size_t)((npix + 255) / 256 + 1) * sizeof(double); }
+
+int ddf_nn_mse(const void *out, int32_t o_cs, const float *target, int64_t npix, const float *weights4, void *dout,
+               double *loss_dev, void *workspace, void *stream)
+{
+    if (o_cs < 4) return fail(DDF_ERR_ARG, "mse: at least 4 output channels");
+    hipStream_t st = (hipStream_t)stream;
+    const int nb = (int)((npix + 255) / 256);
+    double *part = (double *)workspace;
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, (const __bf16 *)out, o_cs, target, npix, weights4[0],
+                       weights4[1], weights4[2], weights4[3], (__bf16 *)dout, part);
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(64), 0, st, part, nb, loss_dev);
+    return check_launch();
+}
+
+int ddf_nn_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float beta1, float beta2, float eps,
+                int64_t step, float weight_decay, void *stream)
+{
+    if (step < 1) return fail(DDF_ERR_ARG, "adam: step counts from 1");
+    const float c1 = 1.0f - std::pow(beta1, (float)step), c2 = 1.0f - std::pow(beta2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, w, g, m, v, n, lr, beta1, beta2,
+                       eps, c1, c2, weight_decay);
+    return check_launch();
+}
+
+int ddf_nn_cast_weights(const float *w, int32_t Cout, int32_t Cin, int32_t Cout_p, int32_t Cin_p, void *wf, void *wd,
+                        void *stream)
+{
+    if (Cout_p < Cout || Cin_p < Cin) return fail(DDF_ERR_ARG, "cast_weights: padded sizes smaller than the real ones");
+    hipLaunchKernelGGL(k_cast_weights, dim3(blocks_for((int64_t)9 * Cout_p * Cin_p)), dim3(256), 0, (hipStream_t)stream,
+                       w, Cout, Cin, Cout_p, Cin_p, (__bf16 *)wf, (__bf16 *)wd);
+    return check_launch();
+}
+
+int ddf_nn_cavity_inputs(const float *re, const float *u, int32_t N, int32_t H, int32_t W, int32_t C, float re_lo,
+                         float re_hi, float u_ref, void *x, void *stream)
+{
+    if (C < 3) return fail(DDF_ERR_ARG, "cavity_inputs: at least 3 channels");
+    hipLaunchKernelGGL(k_cavity_inputs, dim3(blocks_for((int64_t)N * H * W)), dim3(256), 0, (hipStream_t)stream, re, u, N,
+                       H, W, C, std::log(re_lo), std::log(re_hi), u_ref, (__bf16 *)x);
+    return check_launch();
+}
+
+int ddf_nn_cavity_targets(const double *rho, const double *ux, const double *uy, const double *phi, const float *u,
+                          int32_t N, int32_t HW, float *t, void *stream)
+{
+    hipLaunchKernelGGL(k_cavity_targets, dim3(blocks_for((int64_t)N * HW)), dim3(256), 0, (hipStream_t)stream, rho, ux,
+                       uy, phi, u, N, HW, t);
+    return check_launch();
+}
+
+int ddf_nn_cavity_fields(const void *out, int32_t o_cs, const float *u, int32_t N, int32_t HW, double *rho, double *ux,
+                         double *uy, double *phi, void *stream)
+{
+    hipLaunchKernelGGL(k_cavity_fields, dim3(blocks_for((int64_t)N * HW)), dim3(256), 0, (hipStream_t)stream,
+                       (const __bf16 *)out, o_cs, u, N, HW, rho, ux, uy, phi);
+    return check_launch();
+}
+
+}  // extern "C"

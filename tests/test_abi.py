@@ -12,9 +12,12 @@ from paper_1908_06742_amd import _lib as L
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "ddf.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ddf_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in ("ddf.h", "ddf_nn.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(ddf_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():

@@ -1,0 +1,222 @@
+"""GPU tests of the surrogate-network kernels against the FP64 NumPy reference
+(oracle/unet.py), fed with the same BF16-rounded inputs and weights.
+
+Bars: BF16 outputs of a convolution carry one BF16 rounding (relative 2^-9) on top of
+FP32 accumulation, so forward and data-gradient outputs are compared at 1e-2 of the
+output scale; weight and bias gradients accumulate in FP32 from BF16 operands and are
+compared at 1e-3.  The whole network is compared with a reference that rounds to BF16
+where the kernels store (oracle/unet.py's quantiser): what is left is FP32 against FP64
+accumulation order flipping an occasional BF16 rounding, bounded at 5e-3 for the
+output and the gradient vector and 2e-2 per layer; the output is also kept within
+3e-2 of the exact FP64 network."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import unet as U
+from paper_1908_06742_amd import _lib as L
+from paper_1908_06742_amd.surrogate import UNet
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def p(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def bf(a):
+    """numpy -> bf16 device tensor, and the rounded values back as float64."""
+    t = torch.tensor(np.asarray(a, np.float32)).to(torch.bfloat16).to(DEV).contiguous()
+    return t, t.float().cpu().numpy().astype(np.float64)
+
+
+def np_of(t, shape):
+    return t.float().cpu().numpy().astype(np.float64).reshape(shape)
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30))
+
+
+def s0():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@pytest.mark.parametrize("B,H,W,Cin,Cout", [(2, 8, 16, 32, 64), (1, 16, 16, 48, 32), (1, 4, 8, 16, 32)])
+@pytest.mark.parametrize("relu", [0, 1])
+def test_conv3x3_forward(B, H, W, Cin, Cout, relu):
+    r = np.random.default_rng(Cin + Cout + relu)
+    xt, x = bf(r.standard_normal((B, H, W, Cin)))
+    w = r.standard_normal((9, Cout, Cin)) / np.sqrt(9 * Cin)
+    wft, wq = bf(w)
+    b = r.standard_normal(Cout).astype(np.float32)
+    bt = torch.tensor(b, device=DEV)
+    out = torch.zeros(B * H * W * Cout, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_conv3x3(p(xt), B, H, W, Cin, Cin, 0, p(wft), p(bt), p(out), Cout, Cout, 0, relu, 0, s0()))
+    ref = U.conv3x3(x, wq.reshape(9, Cout, Cin), b.astype(np.float64))
+    if relu:
+        ref = np.maximum(ref, 0)
+    assert rel(np_of(out, ref.shape), ref) < 1e-2
+
+
+def test_conv3x3_slices_and_accumulate():
+    B, H, W, Cin, Cout = 1, 8, 8, 32, 32
+    r = np.random.default_rng(5)
+    # input is channels [16, 48) of a 64-channel tensor; output goes to channels [32, 64) of a 96-channel one
+    big, bigq = bf(r.standard_normal((B, H, W, 64)))
+    wt, wq = bf(r.standard_normal((9, Cout, Cin)) / 17)
+    out0, out0q = bf(r.standard_normal((B, H, W, 96)))
+    L.check(L.lib().ddf_nn_conv3x3(p(big), B, H, W, Cin, 64, 16, p(wt), None, p(out0), Cout, 96, 32, 0, 1, s0()))
+    ref = out0q.copy()
+    ref[..., 32:64] += U.conv3x3(bigq[..., 16:48], wq.reshape(9, Cout, Cin))
+    got = np_of(out0, ref.shape)
+    assert rel(got[..., 32:64], ref[..., 32:64]) < 1e-2
+    assert np.array_equal(got[..., :32], out0q[..., :32]) and np.array_equal(got[..., 64:], out0q[..., 64:])
+
+
+def test_conv3x3_data_and_weight_gradients():
+    B, H, W, Cin, Cout = 2, 8, 16, 32, 64
+    r = np.random.default_rng(7)
+    xt, x = bf(r.standard_normal((B, H, W, Cin)))
+    w = (r.standard_normal((9, Cout, Cin)) / np.sqrt(9 * Cin)).astype(np.float32)
+    wmaster = torch.tensor(w, device=DEV)
+    wf = torch.empty(9 * Cout * Cin, dtype=torch.bfloat16, device=DEV)
+    wd = torch.empty_like(wf)
+    L.check(L.lib().ddf_nn_cast_weights(p(wmaster), Cout, Cin, Cout, Cin, p(wf), p(wd), s0()))
+    wq = np_of(wf, (9, Cout, Cin))
+    dyt, dy = bf(r.standard_normal((B, H, W, Cout)))
+    dx = torch.zeros(B * H * W * Cin, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_conv3x3(p(dyt), B, H, W, Cout, Cout, 0, p(wd), None, p(dx), Cin, Cin, 0, 0, 0, s0()))
+    rdx, rdw, rdb = U.conv3x3_backward(x, wq, dy)
+    assert rel(np_of(dx, rdx.shape), rdx) < 1e-2
+    ws = torch.empty(L.lib().ddf_nn_wgrad_workspace_bytes(B, H, W, Cin, Cout, None), dtype=torch.uint8, device=DEV)
+    dw = torch.zeros(9 * Cout * Cin, dtype=torch.float32, device=DEV)
+    db = torch.zeros(Cout, dtype=torch.float32, device=DEV)
+    L.check(L.lib().ddf_nn_conv3x3_wgrad(p(xt), B, H, W, Cin, Cin, 0, p(dyt), Cout, Cout, p(dw), p(db), 0, p(ws), s0()))
+    assert rel(dw.cpu().numpy().reshape(9, Cout, Cin), rdw) < 1e-3
+    assert rel(db.cpu().numpy(), rdb) < 1e-3
+
+
+def test_pool_up_slice_relu_kernels():
+    r = np.random.default_rng(9)
+    B, H, W, C = 2, 8, 8, 16
+    xt, x = bf(r.standard_normal((B, H, W, C)))
+    pooled = torch.empty(B * H * W * C // 4, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_pool2(p(xt), B, H, W, C, p(pooled), s0()))
+    assert rel(np_of(pooled, (B, H // 2, W // 2, C)), U.pool2(x)) < 8e-3
+    up = torch.zeros(B * H * W * 24, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_up2(p(pooled), B, H // 2, W // 2, C, p(up), 24, 8, s0()))
+    pq = np_of(pooled, (B, H // 2, W // 2, C))
+    assert np.array_equal(np_of(up, (B, H, W, 24))[..., 8:24], U.up2(pq))
+    gt, g = bf(r.standard_normal((B, H, W, 24)))
+    din = torch.empty(B * H * W * C // 4, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_up2_bwd(p(gt), B, H // 2, W // 2, C, 24, 8, p(din), s0()))
+    assert rel(np_of(din, pq.shape), U.up2_backward(g[..., 8:24])) < 8e-3
+    dp = torch.zeros(B * H * W * C, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_pool2_bwd(p(din), B, H, W, C, p(dp), 0, s0()))
+    assert rel(np_of(dp, x.shape), U.pool2_backward(np_of(din, pq.shape))) < 8e-3
+    dst = torch.zeros(B * H * W * 40, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_slice(p(xt), C, 0, p(dst), 40, 24, B * H * W, C, 0, s0()))
+    assert np.array_equal(np_of(dst, (B, H, W, 40))[..., 24:40], x)
+    gg = xt.clone()
+    L.check(L.lib().ddf_nn_relu_bwd(p(gg), p(xt), gg.numel(), s0()))
+    assert np.array_equal(np_of(gg, x.shape), np.where(x > 0, x, 0.0))
+
+
+def test_mse_and_adam():
+    r = np.random.default_rng(11)
+    npix = 4 * 16 * 16
+    ot, o = bf(r.standard_normal((npix, 32)))
+    t = r.standard_normal((npix, 4)).astype(np.float32)
+    tt = torch.tensor(t, device=DEV)
+    wts = (C.c_float * 4)(1.0, 0.5, 2.0, 1.5)
+    dout = torch.empty_like(ot)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    ws = torch.empty(L.lib().ddf_nn_mse_workspace_bytes(npix), dtype=torch.uint8, device=DEV)
+    L.check(L.lib().ddf_nn_mse(p(ot), 32, p(tt), npix, wts, p(dout), p(loss), p(ws), s0()))
+    rl, rg = U.mse(o[:, :4].reshape(1, 1, npix, 4), t.astype(np.float64).reshape(1, 1, npix, 4),
+                   np.array([1.0, 0.5, 2.0, 1.5]))
+    rg = rg.reshape(npix, 4)
+    assert abs(loss.item() - rl) / rl < 1e-6
+    d = np_of(dout, (npix, 32))
+    assert rel(d[:, :4], rg) < 8e-3 and np.all(d[:, 4:] == 0)
+    n = 1000
+    w = r.standard_normal(n).astype(np.float32)
+    g = r.standard_normal(n).astype(np.float32)
+    tw, tg = torch.tensor(w, device=DEV), torch.tensor(g, device=DEV)
+    tm, tv = torch.zeros_like(tw), torch.zeros_like(tw)
+    for step in (1, 2):
+        L.check(L.lib().ddf_nn_adam(p(tw), p(tg), p(tm), p(tv), n, 1e-3, 0.9, 0.999, 1e-8, step, 0.0, s0()))
+    m = v = 0.0
+    ww = w.astype(np.float64)
+    for step in (1, 2):
+        m = 0.9 * m + 0.1 * g
+        v = 0.999 * v + 0.001 * g * g
+        ww = ww - 1e-3 * (m / (1 - 0.9 ** step)) / (np.sqrt(v / (1 - 0.999 ** step)) + 1e-8)
+    assert np.max(np.abs(tw.cpu().numpy() - ww)) < 1e-6
+
+
+@pytest.mark.parametrize("levels,H", [(3, 32), (4, 32)])
+def test_unet_forward_backward_against_reference(levels, H):
+    B, W = 2, H
+    net = UNet(base=32, levels=levels, device=DEV, seed=1)
+    r = np.random.default_rng(13)
+    prm = net.params_numpy()
+    for k in prm:
+        if k.endswith(".b"):
+            prm[k] = 0.05 * r.standard_normal(prm[k].shape)
+    net.set_params_numpy(prm)
+    re = torch.tensor([150.0, 2500.0], device=DEV)
+    u = torch.tensor([0.06, 0.09], device=DEV)
+    net.inputs(re, u, H, W)
+    x = np_of(net.x, (B, H, W, 32))[..., :3]
+    out = net.forward(B, H, W)
+    # the reference uses the BF16-rounded weights the GPU actually multiplies
+    pq = {}
+    for name, ci, co, _ in net.table:
+        cip, cop = net._pdims(name, ci, co)
+        pq[name + ".w"] = np_of(net.wf[name], (9, cop, cip))[:, :co, :ci]
+        pq[name + ".b"] = prm[name + ".b"]
+    # the BF16-storage reference rounds where the kernels round: differences left are
+    # accumulation order (FP32 on the matrix cores against FP64), which flips an
+    # occasional BF16 rounding
+    q = U.bf16_round
+    ref, cache = U.forward(pq, x, base=32, levels=levels, cout=4, q=q)
+    got = np_of(out, (B, H, W, 32))[..., :4]
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 5e-3
+    exact, _ = U.forward(pq, x, base=32, levels=levels, cout=4)
+    assert np.linalg.norm(got - exact) / np.linalg.norm(exact) < 3e-2
+    target = r.standard_normal((B, H, W, 4)).astype(np.float32)
+    tt = torch.tensor(target, device=DEV).reshape(-1)
+    net.loss_and_grad(tt, B, H, W)
+    net.backward(B, H, W)
+    _, dref = U.mse(ref, target.astype(np.float64), np.ones(4))
+    gref = U.backward(pq, cache, q(dref), base=32, levels=levels, cout=4, q=q)
+    gg = net.grads_numpy()
+    errs = {}
+    for name in gref:
+        errs[name] = np.linalg.norm(gg[name] - gref[name]) / max(np.linalg.norm(gref[name]), 1e-30)
+    print("largest per-layer gradient errors:", sorted(errs.items(), key=lambda kv: -kv[1])[:4])
+    for name, e in errs.items():
+        assert e < 2e-2, (name, e)
+    a = np.concatenate([gg[k].ravel() for k in sorted(gref)])
+    b = np.concatenate([gref[k].ravel() for k in sorted(gref)])
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 5e-3
+
+
+def test_training_reduces_loss():
+    torch.manual_seed(0)
+    B, H, W = 4, 32, 32
+    net = UNet(base=32, levels=4, device=DEV, seed=2)
+    re = torch.tensor([120.0, 600.0, 1800.0, 4000.0], device=DEV)
+    u = torch.tensor([0.05, 0.07, 0.08, 0.1], device=DEV)
+    yy, xx = torch.meshgrid(torch.linspace(0, 1, H, device=DEV), torch.linspace(0, 1, W, device=DEV), indexing="ij")
+    tgt = torch.stack([torch.stack([torch.sin(3 * xx) * yy * (k + 1) / 4, xx * yy, 0.1 * yy, yy * yy], dim=-1)
+                       for k in range(B)]).float().reshape(-1)
+    losses = []
+    for it in range(60):
+        losses.append(net.train_step(re, u, tgt, H, W, lr=2e-3).item())
+    assert losses[-1] < 0.2 * losses[0], (losses[0], losses[-1])
