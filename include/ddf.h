@@ -201,11 +201,15 @@ int ddf_batch_get_tiling(const ddf_batch *b, int32_t *bx_max, int32_t *blocks_pe
 int ddf_batch_autotune(ddf_batch *b, int32_t steps_per_trial, int32_t *bx_max, int32_t *blocks_per_cu,
                        float *best_ms_per_step, void *stream);
 /* active[i] != 0 keeps instance i in the step list (all instances start active); inactive
- * instances keep their state and still appear in reductions.  Rebuilds the list and
- * invalidates the captured graph. */
+ * instances keep their state and still appear in reductions (with a zero residual).
+ * Needs an even step count (DDF_ERR_STATE otherwise): an inactive instance holds an
+ * even-step state, so while one is inactive ddf_batch_reduce also needs an even step
+ * count.  Rebuilds the list and invalidates the captured graph. */
 int ddf_batch_set_active(ddf_batch *b, const uint8_t *active);
 /* Re-initialise instance i alone at equilibrium from dense FP64 device fields of its
- * size (same rule as ddf_init_equilibrium); the batch step count must be even. */
+ * size (same rule as ddf_init_equilibrium); the batch step count must be even.  The
+ * next ddf_batch_reduce measures instance i's residual against the state before the
+ * re-initialisation, so take one reduction before reading its residual again. */
 int ddf_batch_init_instance(ddf_batch *b, int32_t i, const double *rho, const double *ux, const double *uy,
                             const double *phi, void *stream);
 /* Steps per captured graph (even; 0 = always launch eagerly). */

@@ -440,6 +440,9 @@ int ddf_batch_set_active(ddf_batch *b, const uint8_t *active)
 {
     if (!b) return fail(DDF_ERR_ARG, "batch is NULL");
     if (!active) return fail(DDF_ERR_ARG, "active is NULL");
+    // an instance leaves and re-enters the step list in the natural slot order, so its
+    // stored state stays readable as an even-step state while it is out
+    if (b->step & 1) return fail(DDF_ERR_STATE, "set_active needs an even step count (natural slot order)");
     for (int i = 0; i < b->n; ++i) b->active[i] = active[i] ? 1 : 0;
     return apply_tiling(b, b->bx_max, b->bpc, b->cap_stream);
 }
@@ -595,6 +598,14 @@ int ddf_batch_autotune(ddf_batch *b, int32_t steps_per_trial, int32_t *bx_max_ou
     return DDF_OK;
 }
 
+}  // extern "C"
+
+// Slot order of instance i's stored state: an inactive instance was taken out at an even
+// step count and has not moved since.
+static bool inst_odd(const ddf_batch *b, int i) { return b->active[i] && (b->step & 1) != 0; }
+
+extern "C" {
+
 int ddf_batch_reduce(ddf_batch *b, double *out, void *stream)
 {
     if (!b) return fail(DDF_ERR_ARG, "batch is NULL");
@@ -602,6 +613,9 @@ int ddf_batch_reduce(ddf_batch *b, double *out, void *stream)
     if (!b->initialised) return fail(DDF_ERR_STATE, "reduce before init");
     hipStream_t st = (hipStream_t)stream;
     const bool odd = (b->step & 1) != 0;
+    if (odd)
+        for (int i = 0; i < b->n; ++i)
+            if (!b->active[i]) return fail(DDF_ERR_STATE, "reduce at an odd step count while an instance is inactive");
     const int sv = b->snap_valid ? 1 : 0;
     with_storage(b->storage, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
@@ -651,7 +665,7 @@ int ddf_batch_extract(ddf_batch *b, int32_t i, void *out, uint32_t mask, int32_t
     const Geom G = make_geom(b->p[i]);
     with_storage(b->storage, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        launch_extract<S>(G, b->P[i].of<S>(), has_walls(b->p[i]), (b->step & 1) != 0, (char *)b->f + b->off[i] * s,
+        launch_extract<S>(G, b->P[i].of<S>(), has_walls(b->p[i]), inst_odd(b, i), (char *)b->f + b->off[i] * s,
                           (char *)b->g + b->off[i] * s, b->step, b->p[i].scalar_model, out, out_dtype, mask,
                           (hipStream_t)stream);
         return 0;
@@ -670,7 +684,7 @@ int ddf_batch_get_populations(ddf_batch *b, int32_t i, void *f, void *g, int32_t
     const Geom G = make_geom(b->p[i]);
     with_storage(b->storage, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        launch_get<S>(G, b->P[i].of<S>(), has_walls(b->p[i]), (b->step & 1) != 0, (char *)b->f + b->off[i] * s,
+        launch_get<S>(G, b->P[i].of<S>(), has_walls(b->p[i]), inst_odd(b, i), (char *)b->f + b->off[i] * s,
                       (char *)b->g + b->off[i] * s, f, g, dtype, (hipStream_t)stream);
         return 0;
     });

@@ -37,27 +37,51 @@ def run_to_steady(lat, tol=1e-8, max_steps=200_000, check_every=100, log=None):
             "seconds": time.perf_counter() - t0}
 
 
-def batch_run_to_steady(batch, tol=1e-8, max_steps=200_000, check_every=100):
+def batch_run_to_steady(batch, tol=1e-8, max_steps=200_000, check_every=100, freeze_converged=True, log=None,
+                        log_every=50, max_seconds=None):
     """Steps the whole batch until every instance has converged (or gone non-finite)
-    or max_steps; returns per-instance status and the step count at convergence."""
+    or max_steps; returns per-instance status and the step count at convergence.
+
+    With freeze_converged, an instance leaves the step list once it has converged or
+    gone non-finite (ddf_batch_set_active), so the remaining instances run alone; its
+    state stays as it was at convergence.  max_seconds bounds the wall time: the run
+    stops at the first check past it and unfinished instances report "max_steps"."""
+    if check_every % 2 or max_steps % 2 or batch.step_count % 2:
+        raise ValueError("check_every, max_steps and the batch step count must be even (active-list changes)")
     n = batch.n
     batch.reduce()
     done_at = np.full(n, -1, dtype=np.int64)
     bad = np.zeros(n, dtype=bool)
+    active = np.ones(n, dtype=bool)
     t0 = time.perf_counter()
     steps = 0
     last = None
+    checks = 0
     while steps < max_steps:
         k = min(check_every, max_steps - steps)
         batch.step(k)
         steps += k
         s = batch.reduce()
-        last = s
+        checks += 1
         bad |= s["nonfinite"] > 0
         conv = (s["res_u"] < tol) & (s["res_phi"] < tol) & (done_at < 0) & ~bad
         done_at[conv] = steps
-        if np.all((done_at >= 0) | bad):
+        if last is None:
+            last = {k2: v.copy() for k2, v in s.items()}
+        else:
+            # frozen instances report a zero residual: keep the values they converged with
+            for k2, v in s.items():
+                last[k2][active] = v[active]
+        finished = (done_at >= 0) | bad
+        if log is not None and (checks % log_every == 0 or np.all(finished)):
+            log(steps, int(np.sum(finished)), n, time.perf_counter() - t0)
+        if np.all(finished) or (max_seconds is not None and time.perf_counter() - t0 > max_seconds):
             break
+        if freeze_converged and np.any(active & finished) and (batch.step_count % 2 == 0):
+            active &= ~finished
+            batch.set_active(active)
+    if freeze_converged and not np.all(active):
+        batch.set_active(np.ones(n, dtype=bool))
     status = np.where(bad, "nonfinite", np.where(done_at >= 0, "converged", "max_steps"))
     return {"status": status, "steps_to_converge": done_at, "steps": steps, "stats": last,
             "seconds": time.perf_counter() - t0}

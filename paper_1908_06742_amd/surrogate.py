@@ -10,7 +10,7 @@ buffers (torch) and sequences the calls.
 
 The lattice Boltzmann solver stays the judge: a prediction only initialises the
 lattice, and `warm_start_batch` falls back to a cold start for every instance whose
-residual after the first check is above the fallback threshold or non-finite.
+residual after the first check (100 steps) is above 1e-2 or non-finite.
 """
 from __future__ import annotations
 
@@ -304,6 +304,94 @@ class UNet:
         L.check(L.lib().ddf_nn_cavity_fields(_p(out), COUT_P, _p(u), B, H * W, _p(f[0]), _p(f[1]), _p(f[2]),
                                              _p(f[3]), self._s()))
         return f
+
+
+def predict_batch_fields(net, re, u, H, W, chunk=16):
+    """Network prediction for every (re[i], u[i]) as concatenated FP64 device fields
+    (rho, ux, uy, phi), each [N, H, W], evaluated `chunk` samples at a time."""
+    N = re.numel()
+    out = [torch.empty((N, H, W), dtype=torch.float64, device=net.device) for _ in range(4)]
+    for a in range(0, N, chunk):
+        b = min(N, a + chunk)
+        f = net.predict_fields(re[a:b].contiguous(), u[a:b].contiguous(), H, W)
+        for k in range(4):
+            out[k][a:b].copy_(f[k])
+    return out
+
+
+def warm_start_batch(net, batch, re, u, cold_fields, check_steps=100, fallback_tol=1e-2, chunk=16):
+    """Initialises every instance of `batch` (equal H x W cavities, instance order of
+    re and u) at equilibrium with the network's predicted fields, advances check_steps
+    steps and re-initialises at its cold state (cold_fields(i) -> (rho, ux, uy, phi))
+    every instance whose velocity or scalar residual over those steps exceeds
+    fallback_tol or that holds non-finite values.  Returns the fallback mask (numpy bool).
+    The lattice stays the judge: the prediction is only an initial state."""
+    p0 = batch.problems[0]
+    H, W = p0.ny, p0.nx
+    if any(p.nx != W or p.ny != H for p in batch.problems):
+        raise ValueError("warm_start_batch needs instances of one size")
+    if check_steps % 2:
+        raise ValueError("check_steps must be even")
+    fields = predict_batch_fields(net, re, u, H, W, chunk)
+    batch.init_device(*fields)
+    del fields
+    batch.reduce(raise_nonfinite=False)
+    batch.step(check_steps)
+    s = batch.reduce(raise_nonfinite=False)
+    ru, rp = s["res_u"], s["res_phi"]
+    bad = (s["nonfinite"] > 0) | ~np.isfinite(ru) | ~np.isfinite(rp) | (ru > fallback_tol) | (rp > fallback_tol)
+    for i in np.nonzero(bad)[0]:
+        batch.init_instance(int(i), *cold_fields(int(i)))
+    return bad
+
+
+def train(net, re, u, targets, H, W, iters, batch_size=8, lr=1e-3, lr_min=1e-5, seed=0, log=None, log_every=100):
+    """Adam on the weighted MSE with a cosine learning-rate schedule, on minibatches
+    drawn without replacement (reshuffled every pass) from the N samples
+    (re, u: float32 device [N]; targets: float32 device [N * H * W * 4])."""
+    N = re.numel()
+    tv = targets.view(N, H * W * 4)
+    gen = torch.Generator().manual_seed(seed)
+    order, pos = torch.randperm(N, generator=gen), 0
+    hist = []
+    for it in range(iters):
+        if pos + batch_size > N:
+            order, pos = torch.randperm(N, generator=gen), 0
+        idx = order[pos:pos + batch_size].to(net.device)
+        pos += batch_size
+        lr_t = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * it / max(1, iters)))
+        loss = net.train_step(re[idx].contiguous(), u[idx].contiguous(), tv[idx].reshape(-1).contiguous(), H, W, lr_t)
+        if log is not None and (it % log_every == 0 or it == iters - 1):
+            v = loss.item() / (batch_size * H * W)
+            hist.append((it, v))
+            log(it, v, lr_t)
+    return hist
+
+
+def evaluate_loss(net, re, u, targets, H, W, chunk=16):
+    """Mean squared error per pixel (summed over the four channels) over N samples."""
+    N = re.numel()
+    tv = targets.view(N, H * W * 4)
+    tot = 0.0
+    for a in range(0, N, chunk):
+        b = min(N, a + chunk)
+        net.inputs(re[a:b].contiguous(), u[a:b].contiguous(), H, W)
+        net.forward(b - a, H, W)
+        tot += net.loss_and_grad(tv[a:b].reshape(-1).contiguous(), b - a, H, W).item()
+    return tot / (N * H * W)
+
+
+def save_weights(net, path, **meta):
+    np.savez_compressed(path, w=net.w.detach().cpu().numpy(), base=np.int32(net.base), levels=np.int32(net.levels),
+                        **{k: np.asarray(v) for k, v in meta.items()})
+
+
+def load_weights(path, device="cuda"):
+    with np.load(path, allow_pickle=False) as z:
+        net = UNet(base=int(z["base"]), levels=int(z["levels"]), device=device)
+        net.load_state_dict({"w": z["w"], "base": int(z["base"]), "levels": int(z["levels"])})
+        meta = {k: z[k] for k in z.files if k not in ("w", "base", "levels")}
+    return net, meta
 
 
 def make_targets(rho, ux, uy, phi, u):

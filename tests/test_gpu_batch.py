@@ -145,3 +145,61 @@ def test_per_instance_statistics_and_nonfinite_flag():
         m = lat.reduce()
         assert abs(m["mass"] - s["mass"][i]) <= 1e-12 * abs(m["mass"]), i
         assert abs(m["scalar"] - s["scalar"][i]) <= 1e-12 * abs(m["scalar"]) + 1e-12, i
+
+
+def test_inactive_instances_hold_state_and_the_rest_match_a_full_batch():
+    say("case: batch active mask")
+    items = mixed_problems("f32")
+    full = Batch([p for p, _ in items], device=DEV)
+    part = Batch([p for p, _ in items], device=DEV)
+    for b in (full, part):
+        b.set_graph(20)
+        b.init([f for _, f in items]).step(10)
+    frozen = {i: part.get_populations(i, raw=True) for i in (1, 3)}
+    part.set_active([i not in frozen for i in range(len(items))])
+    full.step(47)      # odd count: graph replays plus eager steps
+    part.step(47)
+    for i in range(len(items)):
+        fa, ga = part.get_populations(i, raw=True)
+        if i in frozen:
+            assert torch.equal(fa, frozen[i][0]) and torch.equal(ga, frozen[i][1]), i
+            x = part.extract(i, ["rho"])["rho"]
+            assert torch.isfinite(x).all()
+        else:
+            fb, gb = full.get_populations(i, raw=True)
+            assert torch.equal(fa, fb) and torch.equal(ga, gb), i
+    with pytest.raises(RuntimeError, match="odd step"):
+        part.reduce()
+    part.step(1)
+    s = part.reduce()
+    assert np.all(s["nonfinite"] == 0)
+    with pytest.raises(RuntimeError, match="even step"):
+        part.step(1).set_active([True] * len(items))
+    part.step(1)
+    part.set_active([True] * len(items))
+    part.step(4)
+    assert part.step_count == 10 + 47 + 1 + 1 + 1 + 4
+
+
+def test_init_instance_restarts_one_instance_only():
+    say("case: batch init_instance")
+    items = mixed_problems("f64")
+    b = Batch([p for p, _ in items], device=DEV)
+    b.init([f for _, f in items]).step(30)
+    k = 0   # a cavity at rest with phi = 0.2 (non-zero g, so relative errors are defined)
+    pr, f0 = items[k]
+    others = {i: b.get_populations(i) for i in range(len(items)) if i != k}
+    b.init_instance(k, *f0)
+    fk, gk = (t.cpu().numpy() for t in b.get_populations(k))
+    fo, go, _ = oracle.Oracle(pr, nthreads=8).run(f0, 0)
+    assert rel(fk, fo) < 1e-14 and rel(gk, go) < 1e-14
+    for i, (f, g) in others.items():
+        fa, ga = b.get_populations(i)
+        assert torch.equal(fa, f) and torch.equal(ga, g), i
+    b.step(20)
+    fk, gk = (t.cpu().numpy() for t in b.get_populations(k))
+    fo, go, _ = oracle.Oracle(pr, nthreads=8).run(f0, 20)
+    assert rel(fk, fo) < 1e-12 and rel(gk, go) < 1e-12
+    b.step(1)
+    with pytest.raises(RuntimeError, match="even step"):
+        b.init_instance(k, *f0)

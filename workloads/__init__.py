@@ -293,3 +293,24 @@ def batch_instances(count: int = 256, seed0: int = 4096, side_lo: int = 64, side
                          force_kind="uniform", force=(F, 0.0), storage=storage, rho0=1.0, phi0=0.5)
             out.append(Instance(kind, W, H, re, u, pr))
     return out
+
+
+# --------------------------------------------------------------------------
+# Cavity family of the surrogate study
+# --------------------------------------------------------------------------
+
+SURROGATE_TRAIN_SEED0 = 0
+SURROGATE_HELDOUT_SEED0 = 100_000
+
+
+def surrogate_cases(count: int, seed0: int = SURROGATE_TRAIN_SEED0):
+    """(Re, U) of cavity i from seed seed0 + i: Re log-uniform in [100, 5000],
+    lid speed U ~ U(0.05, 0.1).  Training uses seeds 0.., held-out evaluation
+    seeds 100000.."""
+    out = []
+    for i in range(count):
+        r = np.random.default_rng(seed0 + i)
+        re = float(math.exp(r.uniform(math.log(100.0), math.log(5000.0))))
+        u = float(r.uniform(0.05, 0.1))
+        out.append((re, u))
+    return out
