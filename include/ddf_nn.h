@@ -76,8 +76,9 @@ int ddf_nn_adam(float *w, const float *g, float *m, float *v, int64_t n, float l
 int ddf_nn_cast_weights(const float *w, int32_t Cout, int32_t Cin, int32_t Cout_p, int32_t Cin_p, void *wf, void *wd,
                         void *stream);
 
-/* Lid-driven cavity inputs [N][H][W][C]: wall mask (1 next to a fixed wall, 2 next to the
- * lid at y = H - 1), (log Re - log re_lo) / (log re_hi - log re_lo), U / u_ref, zeros. */
+/* Lid-driven cavity inputs [N][H][W][C], C >= 5: wall mask (1 next to a fixed wall, 2 next
+ * to the lid at y = H - 1), (log Re - log re_lo) / (log re_hi - log re_lo), U / u_ref,
+ * x / (W - 1), y / (H - 1), then zeros. */
 int ddf_nn_cavity_inputs(const float *re, const float *u, int32_t N, int32_t H, int32_t W, int32_t C, float re_lo,
                          float re_hi, float u_ref, void *x, void *stream);
 /* Targets [N][H][W][4] = (u / U, v / U, (rho - 1) / U^2, phi) from dense FP64 fields. */

@@ -304,7 +304,11 @@ __global__ void k_cavity_inputs(const float *__restrict__ re, const float *__res
     o[0] = (__bf16)mask;
     o[1] = (__bf16)((logf(re[n]) - lre_lo) / (lre_hi - lre_lo));
     o[2] = (__bf16)(u[n] / u_ref);
-    for (int c = 3; c < C; ++c) o[c] = (__bf16)0.0f;
+    // node coordinates in [0, 1]: the receptive field of the network is smaller than
+    // the cavity, so position is an input rather than something inferred from walls
+    o[3] = (__bf16)(W > 1 ? (float)px / (float)(W - 1) : 0.0f);
+    o[4] = (__bf16)(H > 1 ? (float)py / (float)(H - 1) : 0.0f);
+    for (int c = 5; c < C; ++c) o[c] = (__bf16)0.0f;
 }
 
 // Normalised training targets from steady fields (dense FP64 [N][H][W] each):
@@ -499,7 +503,8 @@ int ddf_nn_cast_weights(const float *w, int32_t Cout, int32_t Cin, int32_t Cout_
 int ddf_nn_cavity_inputs(const float *re, const float *u, int32_t N, int32_t H, int32_t W, int32_t C, float re_lo,
                          float re_hi, float u_ref, void *x, void *stream)
 {
-    if (C < 3) return fail(DDF_ERR_ARG, "cavity_inputs: at least 3 channels");
+    if (C < 5) return fail(DDF_ERR_ARG, "cavity_inputs: at least 5 channels");
+    if (N < 0 || H < 1 || W < 1) return fail(DDF_ERR_ARG, "cavity_inputs: bad shape");
     hipLaunchKernelGGL(k_cavity_inputs, dim3(blocks_for((int64_t)N * H * W)), dim3(256), 0, (hipStream_t)stream, re, u, N,
                        H, W, C, std::log(re_lo), std::log(re_hi), u_ref, (__bf16 *)x);
     return check_launch();

@@ -1,6 +1,6 @@
 """Surrogate U-Net for steady lid-driven cavities, on the libddf BF16 MFMA kernels.
 
-Maps (wall mask, Re, lid speed) on an H x W grid to normalised steady fields
+Maps (wall mask, Re, lid speed, node coordinates) on an H x W grid to normalised steady fields
 (u / U, v / U, (rho - 1) / U^2, phi).  Four levels of two 3x3 convolutions with
 ReLU (widths base, 2 base, 4 base, 8 base), 2x2 average pooling down, nearest 2x
 upsampling and skip concatenation up, and a 3x3 head.  Activations are NHWC BF16,
@@ -23,7 +23,8 @@ import torch
 from . import _lib as L
 
 RE_LO, RE_HI, U_REF = 100.0, 5000.0, 0.1
-CIN_P = 32     # network input channels (3 used)
+CIN = 5        # mask, log Re, U, x, y
+CIN_P = 32     # network input channels (CIN used)
 COUT_P = 32    # head output channels (4 used)
 
 
@@ -31,7 +32,7 @@ def _p(t):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
 
 
-def layer_table(base=32, levels=4, cin=3, cout=4):
+def layer_table(base=32, levels=4, cin=CIN, cout=4):
     """(name, cin, cout, relu) in forward order."""
     ch = [base * 2 ** k for k in range(levels)]
     out, prev = [], cin
@@ -383,14 +384,16 @@ def evaluate_loss(net, re, u, targets, H, W, chunk=16):
 
 def save_weights(net, path, **meta):
     np.savez_compressed(path, w=net.w.detach().cpu().numpy(), base=np.int32(net.base), levels=np.int32(net.levels),
-                        **{k: np.asarray(v) for k, v in meta.items()})
+                        cin=np.int32(CIN), **{k: np.asarray(v) for k, v in meta.items()})
 
 
 def load_weights(path, device="cuda"):
     with np.load(path, allow_pickle=False) as z:
+        if "cin" not in z.files or int(z["cin"]) != CIN:
+            raise ValueError(f"{path}: weights for a different input encoding (expected {CIN} input channels)")
         net = UNet(base=int(z["base"]), levels=int(z["levels"]), device=device)
         net.load_state_dict({"w": z["w"], "base": int(z["base"]), "levels": int(z["levels"])})
-        meta = {k: z[k] for k in z.files if k not in ("w", "base", "levels")}
+        meta = {k: z[k] for k in z.files if k not in ("w", "base", "levels", "cin")}
     return net, meta
 
 
