@@ -12,9 +12,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libddf.so")
 
-DDF_F64, DDF_F32, DDF_F16, DDF_BF16 = 0, 1, 2, 3
-STORAGE = {"f64": DDF_F64, "f32": DDF_F32, "f16": DDF_F16, "bf16": DDF_BF16}
-STORAGE_BYTES = {DDF_F64: 8, DDF_F32: 4, DDF_F16: 2, DDF_BF16: 2}
+DDF_F64, DDF_F32, DDF_F16, DDF_BF16, DDF_BF16_SR = 0, 1, 2, 3, 4
+STORAGE = {"f64": DDF_F64, "f32": DDF_F32, "f16": DDF_F16, "bf16": DDF_BF16, "bf16sr": DDF_BF16_SR}
+STORAGE_BYTES = {DDF_F64: 8, DDF_F32: 4, DDF_F16: 2, DDF_BF16: 2, DDF_BF16_SR: 2}
 
 DDF_OK, DDF_ERR_ARG, DDF_ERR_UNSUPPORTED, DDF_ERR_HIP, DDF_ERR_NONFINITE, DDF_ERR_STATE = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "DDF_OK", -1: "DDF_ERR_ARG", -2: "DDF_ERR_UNSUPPORTED", -3: "DDF_ERR_HIP",

@@ -24,29 +24,56 @@ static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "diagona
 
 // ---------------------------------------------------------------------------
 // Storage codecs.  Stored value = encode(offset * scale); scale is a power of two.
+// enc takes a 32-bit key naming the population slot and time step; only the
+// stochastically rounded format uses it.
 // ---------------------------------------------------------------------------
-struct bf16 { uint16_t bits; };
+struct bf16 { uint16_t bits; };     // bfloat16, round to nearest even
+struct bf16sr { uint16_t bits; };   // bfloat16, stochastic rounding
+
+// 32-bit integer finaliser (xorshift-multiply rounds; the "lowbias32" constants of
+// C. Wellons' hash prospector): a counter-based source of uniform bits.
+__device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Key of one stored population: its slot index, the time step and the lattice (0 = f,
+// 1 = g).  Distinct (slot, step, lattice) give independent rounding decisions, and the
+// same ones give the same decisions (runs and checkpoint resumes are reproducible).
+__device__ __forceinline__ uint32_t sr_key(int64_t slot, uint32_t step_salt)
+{
+    return ((uint32_t)slot * 0x9e3779b1u) ^ (uint32_t)(slot >> 32) ^ step_salt;
+}
+__device__ __forceinline__ uint32_t sr_step_salt(int64_t t, uint32_t lattice)
+{
+    return mix32((uint32_t)t * 2u + lattice + 0x51ed27u);
+}
 
 template <class S> struct Codec;
 template <> struct Codec<double> {
     using R = double;
     __device__ static double dec(double v) { return v; }
-    __device__ static double enc(double v) { return v; }
+    __device__ static double enc(double v, uint32_t) { return v; }
 };
 template <> struct Codec<float> {
     using R = float;
     __device__ static float dec(float v) { return v; }
-    __device__ static float enc(float v) { return v; }
+    __device__ static float enc(float v, uint32_t) { return v; }
 };
 template <> struct Codec<_Float16> {
     using R = float;
     __device__ static float dec(_Float16 v) { return (float)v; }
-    __device__ static _Float16 enc(float v) { return (_Float16)v; }   // round to nearest even
+    __device__ static _Float16 enc(float v, uint32_t) { return (_Float16)v; }   // round to nearest even
 };
 template <> struct Codec<bf16> {
     using R = float;
     __device__ static float dec(bf16 v) { return __uint_as_float(((uint32_t)v.bits) << 16); }
-    __device__ static bf16 enc(float v)
+    __device__ static bf16 enc(float v, uint32_t)
     {
         uint32_t u = __float_as_uint(v);
         bf16 r;
@@ -54,6 +81,27 @@ template <> struct Codec<bf16> {
             r.bits = (uint16_t)((u >> 16) | 0x40u);
         } else {                                        // round to nearest even
             u += 0x7fffu + ((u >> 16) & 1u);
+            r.bits = (uint16_t)(u >> 16);
+        }
+        return r;
+    }
+};
+// Stochastic rounding: the magnitude rounds up with probability equal to the dropped
+// fraction of a bfloat16 ulp, so the stored value is unbiased and slow changes smaller
+// than half an ulp accumulate in expectation instead of being rounded away.
+template <> struct Codec<bf16sr> {
+    using R = float;
+    __device__ static float dec(bf16sr v) { return __uint_as_float(((uint32_t)v.bits) << 16); }
+    __device__ static bf16sr enc(float v, uint32_t key)
+    {
+        uint32_t u = __float_as_uint(v);
+        bf16sr r;
+        if ((u & 0x7fffffffu) > 0x7f800000u) {          // NaN stays a quiet NaN
+            r.bits = (uint16_t)((u >> 16) | 0x40u);
+        } else if ((u & 0x7f800000u) == 0x7f800000u) {  // infinities unchanged
+            r.bits = (uint16_t)(u >> 16);
+        } else {
+            u += mix32(key) & 0xffffu;
             r.bits = (uint16_t)(u >> 16);
         }
         return r;

@@ -145,9 +145,10 @@ __device__ __forceinline__ void step_node(S *__restrict__ f, S *__restrict__ g, 
     else collide_scalar_mrt(P, M, n, go);
 
     const int64_t cell = (int64_t)y * L.pitch + x;
+    const uint32_t kf = sr_step_salt(t, 0), kg = sr_step_salt(t, 1);
     // rest direction: same slot in both parities
-    f[cell] = Codec<S>::enc(fo[0] * P.scale);
-    g[cell] = Codec<S>::enc(go[0] * P.scale);
+    f[cell] = Codec<S>::enc(fo[0] * P.scale, sr_key(cell, kf));
+    g[cell] = Codec<S>::enc(go[0] * P.scale, sr_key(cell, kg));
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
         int tx, ty;
@@ -165,8 +166,8 @@ __device__ __forceinline__ void step_node(S *__restrict__ f, S *__restrict__ g, 
         } else {
             slot = (int64_t)a * L.plane + (int64_t)ty * L.pitch + tx;
         }
-        f[slot] = Codec<S>::enc(vf * P.scale);
-        g[slot] = Codec<S>::enc(vg * P.scale);
+        f[slot] = Codec<S>::enc(vf * P.scale, sr_key(slot, kf));
+        g[slot] = Codec<S>::enc(vg * P.scale, sr_key(slot, kg));
     }
 }
 
@@ -238,10 +239,12 @@ __global__ __launch_bounds__(kThreads) void k_init(S *__restrict__ f, S *__restr
     scalar_eq(P, M, n);
     populations(n, go);
     const int64_t cell = (int64_t)y * G.L.pitch + x;
+    const uint32_t kf = sr_step_salt(-1, 0), kg = sr_step_salt(-1, 1);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        f[(int64_t)a * G.L.plane + cell] = Codec<S>::enc(fo[a] * P.scale);
-        g[(int64_t)a * G.L.plane + cell] = Codec<S>::enc(go[a] * P.scale);
+        const int64_t s = (int64_t)a * G.L.plane + cell;
+        f[s] = Codec<S>::enc(fo[a] * P.scale, sr_key(s, kf));
+        g[s] = Codec<S>::enc(go[a] * P.scale, sr_key(s, kg));
     }
 }
 
@@ -387,8 +390,8 @@ __global__ __launch_bounds__(kThreads) void k_set(S *__restrict__ f, S *__restri
         if (dtype == 0) {
             const double vf = ((const double *)fi)[a * N + c] - (double)P.rest_f[a] * (double)P.rho0;
             const double vg = ((const double *)gi)[a * N + c] - (double)P.rest_g[a] * (double)P.phi0;
-            f[s] = Codec<S>::enc((R)(vf * (double)P.scale));
-            g[s] = Codec<S>::enc((R)(vg * (double)P.scale));
+            f[s] = Codec<S>::enc((R)(vf * (double)P.scale), sr_key(s, sr_step_salt(-2, 0)));
+            g[s] = Codec<S>::enc((R)(vg * (double)P.scale), sr_key(s, sr_step_salt(-2, 1)));
         } else {
             f[s] = ((const S *)fi)[a * N + c];
             g[s] = ((const S *)gi)[a * N + c];
@@ -563,7 +566,7 @@ inline int validate(const ddf_params *p)
     if (!p) return fail(DDF_ERR_ARG, "params is NULL");
     if (p->nx < 2 || p->ny < 2) return fail(DDF_ERR_ARG, "nx and ny must be >= 2");
     if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(DDF_ERR_ARG, "lattice larger than 2^31 nodes");
-    if (p->storage < DDF_F64 || p->storage > DDF_BF16) return fail(DDF_ERR_ARG, "unknown storage");
+    if (p->storage < DDF_F64 || p->storage > DDF_BF16_SR) return fail(DDF_ERR_ARG, "unknown storage");
     if (p->scalar_model < DDF_SCALAR_MRT || p->scalar_model > DDF_SCALAR_CENTRAL)
         return fail(DDF_ERR_ARG, "unknown scalar model");
     if (p->force_kind < DDF_FORCE_NONE || p->force_kind > DDF_FORCE_PULSATILE)
@@ -595,6 +598,7 @@ int with_storage(int storage, F &&fn)
     case DDF_F64: return fn((double *)nullptr);
     case DDF_F32: return fn((float *)nullptr);
     case DDF_F16: return fn((_Float16 *)nullptr);
+    case DDF_BF16_SR: return fn((bf16sr *)nullptr);
     default: return fn((bf16 *)nullptr);
     }
 }

@@ -12,7 +12,8 @@ import torch
 from . import _lib as L
 
 _TORCH_STORAGE = {L.DDF_F64: torch.float64, L.DDF_F32: torch.float32,
-                  L.DDF_F16: torch.float16, L.DDF_BF16: torch.bfloat16}
+                  L.DDF_F16: torch.float16, L.DDF_BF16: torch.bfloat16,
+                  L.DDF_BF16_SR: torch.bfloat16}
 
 
 def _stream_ptr(stream):

@@ -68,7 +68,7 @@ def test_create_rejects_unaligned_buffers():
 
 
 def test_valid_create_and_sizes():
-    for storage, s in (("f64", 8), ("f32", 4), ("f16", 2), ("bf16", 2)):
+    for storage, s in (("f64", 8), ("f32", 4), ("f16", 2), ("bf16", 2), ("bf16sr", 2)):
         pr = W.Problem(nx=100, ny=37, storage=storage)
         p = L.params_from_problem(pr)
         pitch = L.lib().ddf_pitch(C.byref(p))

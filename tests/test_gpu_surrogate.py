@@ -1,7 +1,8 @@
 """GPU tests of the cavity surrogate's warm start: the trained network (weights shipped
-with the package) shortens the run to a steady state against both a cold start and
-an untrained network, every warm-started steady state is the cold-started one, and
-the fallback re-initialises exactly the instances whose prediction is unusable."""
+with the package) shortens the run to r < 1e-8 at least twofold against both a cold
+start and an untrained network, the warm-started steady states are the cold-started
+ones (u, phi, omega within 1e-3), and the fallback re-initialises exactly the
+instances whose prediction is unusable."""
 import os
 import sys
 
@@ -58,53 +59,43 @@ def steps_to(b, tol, cap):
     return np.where(s >= 0, s, cap), r
 
 
-def test_trained_network_shortens_the_run_to_steady():
-    say("case: surrogate gain, 8 held-out cavities, r < 1e-6")
+def test_trained_network_shortens_the_run_to_steady_and_keeps_its_result():
+    # the 8 lowest-Re held-out cavities converge to r < 1e-8 within the cap from rest
+    say("case: surrogate gain, 8 lowest-Re held-out cavities, r < 1e-8")
     assert os.path.exists(WEIGHTS), "trained weights missing"
-    cases = held_out(8)
+    cases = held_out(8, lowest_re=8)
     re, u = tensors(cases)
-    cap = 60_000
-    b = batch_of(cases)
-    cold_init(b, len(cases))
-    s_cold, _ = steps_to(b, 1e-6, cap)
+    cap = 400_000
+    bc = batch_of(cases)
+    cold_init(bc, len(cases))
+    s_cold, rc = steps_to(bc, 1e-8, cap)
     net, meta = S.load_weights(WEIGHTS, device=DEV)
-    b = batch_of(cases)
-    fb = S.warm_start_batch(net, b, re, u, cold_fields)
+    bw = batch_of(cases)
+    fb = S.warm_start_batch(net, bw, re, u, cold_fields)
     assert not fb.any()
-    s_warm, _ = steps_to(b, 1e-6, cap)
+    s_warm, rw = steps_to(bw, 1e-8, cap)
     s_warm = s_warm + 100
     untrained = S.UNet(base=32, levels=4, device=DEV, seed=0)
-    b = batch_of(cases)
-    fbu = S.warm_start_batch(untrained, b, re, u, cold_fields)
-    s_untr, _ = steps_to(b, 1e-6, cap)
+    bu = batch_of(cases)
+    fbu = S.warm_start_batch(untrained, bu, re, u, cold_fields)
+    s_untr, _ = steps_to(bu, 1e-8, cap)
     s_untr = s_untr + 100
     say(f"steps cold {s_cold.tolist()}\n      warm {s_warm.tolist()}\n untrained {s_untr.tolist()} "
         f"(fallbacks {int(fbu.sum())})")
+    assert np.all(rc["status"] == "converged") and np.all(rw["status"] == "converged")
     assert s_warm.sum() * 2 <= s_cold.sum()
     assert s_warm.sum() * 2 <= s_untr.sum()
-
-
-def test_warm_started_steady_state_is_the_cold_started_one():
-    say("case: surrogate steady state identity, 4 low-Re cavities, r < 1e-8")
-    cases = held_out(4, lowest_re=4)
-    re, u = tensors(cases)
-    net, _ = S.load_weights(WEIGHTS, device=DEV)
-    bc = batch_of(cases)
-    cold_init(bc, len(cases))
-    _, rc = steps_to(bc, 1e-8, 400_000)
-    bw = batch_of(cases)
-    S.warm_start_batch(net, bw, re, u, cold_fields)
-    _, rw = steps_to(bw, 1e-8, 400_000)
-    assert np.all(rc["status"] == "converged") and np.all(rw["status"] == "converged")
+    # the lattice is the judge: the warm-started steady state is the cold-started one
+    # (both stop at r < 1e-8, so they differ by about r over the slowest decay rate)
     for i in range(len(cases)):
         a = bc.extract(i, ["ux", "uy", "phi", "wz"])
         c = bw.extract(i, ["ux", "uy", "phi", "wz"])
         m = a["phi"] >= 0.1
-        for k in ("ux", "uy", "phi"):
-            e = float(torch.linalg.norm(a[k] - c[k]) / torch.linalg.norm(a[k]))
-            assert e < 1e-4, (i, k, e)
+        du = torch.sqrt(torch.sum((a["ux"] - c["ux"]) ** 2 + (a["uy"] - c["uy"]) ** 2))
+        assert float(du / torch.sqrt(torch.sum(a["ux"] ** 2 + a["uy"] ** 2))) < 1e-3, i
+        assert float(torch.linalg.norm(a["phi"] - c["phi"]) / torch.linalg.norm(a["phi"])) < 1e-3, i
         e = float(torch.linalg.norm((a["wz"] - c["wz"])[m]) / torch.linalg.norm(a["wz"][m]))
-        assert e < 1e-3, (i, "wz", e)
+        assert e < 1e-3, (i, e)
 
 
 class _Scripted:
