@@ -45,14 +45,18 @@ class Batch:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            L.lib().ddf_batch_destroy(h)
+            try:
+                L.lib().ddf_batch_destroy(h)
+            except TypeError:      # interpreter shutdown: module globals already cleared
+                pass
             self._h = None
 
     def init(self, fields):
         """fields: list of (rho, ux, uy, phi) per instance (arrays of shape (ny, nx))."""
         cat = []
         for k in range(4):
-            parts = [torch.as_tensor(np.broadcast_to(np.asarray(f[k], np.float64), (p.ny, p.nx))).reshape(-1)
+            parts = [torch.as_tensor(np.ascontiguousarray(np.broadcast_to(np.asarray(f[k], np.float64), (p.ny, p.nx))))
+                     .reshape(-1)
                      for f, p in zip(fields, self.problems)]
             cat.append(torch.cat(parts).to(self.device).contiguous())
         L.check(L.lib().ddf_batch_init_equilibrium(self._h, *[_ptr(t) for t in cat], _stream_ptr(self.stream)))
@@ -68,8 +72,13 @@ class Batch:
 
     def init_instance(self, i, rho, ux, uy, phi):
         p = self.problems[i]
-        fields = [torch.as_tensor(np.broadcast_to(np.asarray(a, np.float64), (p.ny, p.nx)) if not torch.is_tensor(a)
-                                  else a).to(self.device, torch.float64).contiguous() for a in (rho, ux, uy, phi)]
+
+        def dev(a):
+            if not torch.is_tensor(a):
+                a = torch.as_tensor(np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), (p.ny, p.nx))))
+            return a.to(self.device, torch.float64).contiguous()
+
+        fields = [dev(a) for a in (rho, ux, uy, phi)]
         L.check(L.lib().ddf_batch_init_instance(self._h, int(i), *[_ptr(t) for t in fields], _stream_ptr(self.stream)))
         self._keep_i = fields
         return self

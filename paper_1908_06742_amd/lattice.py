@@ -56,7 +56,10 @@ class Lattice:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            L.lib().ddf_destroy(h)
+            try:
+                L.lib().ddf_destroy(h)
+            except TypeError:      # interpreter shutdown: module globals already cleared
+                pass
             self._h = None
 
     # -- state -----------------------------------------------------------------
