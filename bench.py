@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 LB_STEPS_PER_STEP = 100
-BYTES_PER_NODE = {"f64": 288, "f32": 144, "f16": 72, "bf16": 72}
+BYTES_PER_NODE = {"f64": 288, "f32": 144, "f16": 72, "bf16": 72, "bf16sr": 72}
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_vortex8192_f32_counters.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1908_06742_amd", "csrc", n)
                   for n in ("ddf.hip", "ddf_kernels.hpp", "ddf_device.hpp")]
@@ -151,6 +151,57 @@ def run_batch(steps=2000, count=256):
             "hbm_gbs": round(144.0 * nodes * steps / dt / 1e9, 1)}
 
 
+def run_surrogate(count=16, cap=400_000):
+    """Time to r < 1e-8 of the `count` lowest-Re held-out 256^2 cavities (seeds
+    100000..100199), FP32: cold from rest in one batch, and warm from the shipped
+    network's prediction (inference and the fallback check inside the timed region);
+    plus the sequential single-lattice estimate (measured per-step time x cold steps)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1908_06742_amd import Batch
+    from paper_1908_06742_amd import surrogate as S
+    from paper_1908_06742_amd.steady import batch_run_to_steady
+    from paper_1908_06742_amd.surrogate_study import single_step_seconds
+
+    n = 256
+    held = W.surrogate_cases(200, W.SURROGATE_HELDOUT_SEED0)
+    cases = sorted(held, key=lambda c: c[0])[:count]
+    probs = [W.cavity_problem(n, re, u) for re, u in cases]
+    re = torch.tensor([c[0] for c in cases], dtype=torch.float32, device="cuda")
+    u = torch.tensor([c[1] for c in cases], dtype=torch.float32, device="cuda")
+    Batch(probs, device="cuda").autotune(10)
+    net, _ = S.load_weights(os.path.join(ROOT, "paper_1908_06742_amd", "weights", "unet_cavity256.npz"))
+    S.predict_batch_fields(net, re, u, n, n)       # first call allocates the activations
+    b = Batch(probs, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    z = torch.zeros((count, n, n), dtype=torch.float64, device="cuda")
+    b.init_device(torch.ones_like(z), z, z, z)
+    rc = batch_run_to_steady(b, tol=1e-8, max_steps=cap, check_every=100)
+    torch.cuda.synchronize()
+    t_cold = time.perf_counter() - t0
+    del b
+    b = Batch(probs, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fb = S.warm_start_batch(net, b, re, u, lambda i: W.cavity_fields(n))
+    rw = batch_run_to_steady(b, tol=1e-8, max_steps=cap - 100, check_every=100)
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    sc = np.where(rc["steps_to_converge"] >= 0, rc["steps_to_converge"], cap)
+    sw = np.where(rw["steps_to_converge"] >= 0, rw["steps_to_converge"] + 100, cap)
+    t_single = single_step_seconds(cases[0], n, steps=10_000) * float(sc.sum())
+    return {"workload": f"{count} lowest-Re held-out 256^2 cavities, FP32, to r < 1e-8 (cap {cap})",
+            "seconds_cold_single_estimate": round(t_single, 2), "seconds_cold_batch": round(t_cold, 2),
+            "seconds_warm_batch": round(t_warm, 2), "speedup_vs_cold_single": round(t_single / t_warm, 2),
+            "speedup_vs_cold_batch": round(t_cold / t_warm, 2), "fallbacks": int(fb.sum()),
+            "converged_cold": int(np.sum(rc["status"] == "converged")),
+            "converged_warm": int(np.sum(rw["status"] == "converged")),
+            "steps_cold_over_warm": round(float(sc.sum() / sw.sum()), 2)}
+
+
 def cpu_baseline(budget_s=12.0):
     """The FP64 oracle timed on the host cores on a bounded sample of the same
     workload: a 256 x 256 window of the vortex field run as a periodic lattice, in
@@ -183,9 +234,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--size", type=int, default=8192)
-    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16", "bf16"])
+    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16", "bf16", "bf16sr"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the 1024^2 cavity and 256-instance batch lines")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 1024^2 cavity, 256-instance batch and surrogate time-to-steady lines")
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--variants", action="store_true", help="also time FP16/BF16/FP64 storage of the same field")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -252,9 +304,11 @@ def main():
         line["extras"] = {"cavity1024_f32": run_cavity()}
         print("[bench] extra: batch of 256 instances f32", file=sys.stderr, flush=True)
         line["extras"]["batch256_f32"] = run_batch(args.batch_steps)
+        print("[bench] extra: surrogate warm start vs cold start", file=sys.stderr, flush=True)
+        line["extras"]["surrogate256_time_to_steady"] = run_surrogate()
     if args.variants:
         var = []
-        for st, L in (("f16", 8192), ("bf16", 8192), ("f64", 8192)):
+        for st, L in (("f16", 8192), ("bf16", 8192), ("bf16sr", 8192), ("f64", 8192)):
             print(f"[bench] variant {L}^2 {st}", file=sys.stderr, flush=True)
             v = run_gpu(L, st, 3, 1)
             ach = BYTES_PER_NODE[st] * v["nodes"] / (v["kernel_ms"] * 1e-3) / 1e9

@@ -182,7 +182,12 @@ size_t ddf_batch_population_bytes(int32_t n, const ddf_params *ps);
 /* Bytes of device workspace (descriptors, tile list, reduction partials, snapshots). */
 size_t ddf_batch_workspace_bytes(int32_t n, const ddf_params *ps);
 /* Validate every instance as ddf_create does and bind the caller's buffers
- * (256-byte aligned).  Uploads the instance descriptors (synchronous). */
+ * (256-byte aligned).  Uploads the instance descriptors (synchronous).
+ * ddf_batch_create, ddf_batch_set_tiling, ddf_batch_set_active, ddf_batch_set_graph
+ * (when a graph is captured) and ddf_batch_destroy first wait for all work on the
+ * device (hipDeviceSynchronize): the buffers may be memory the caller's allocator has
+ * just recycled from tensors that queued work still writes, and a replay may still be
+ * reading the lists they replace. */
 int ddf_batch_create(int32_t n, const ddf_params *ps, void *pop_f, void *pop_g, void *workspace, ddf_batch **out);
 void ddf_batch_destroy(ddf_batch *b);
 int32_t ddf_batch_size(const ddf_batch *b);

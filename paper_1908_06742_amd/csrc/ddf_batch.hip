@@ -209,6 +209,17 @@ void fill_desc(const ddf_batch *b, std::vector<InstDesc<R>> &d, std::vector<Tile
     }
 }
 
+// The host-side setters upload descriptors and tile lists on the private capture
+// stream, which is not ordered after the caller's streams.  Their buffers may have been
+// handed out by the caller's allocator while earlier work of the caller still writes
+// that memory, and a replay of the old graph may still be reading the lists: wait for
+// the whole device first.
+int quiesce()
+{
+    DDF_HIP_TRY(hipDeviceSynchronize());
+    return DDF_OK;
+}
+
 void drop_graph(ddf_batch *b)
 {
     if (b->captured_steps) {
@@ -382,7 +393,8 @@ int ddf_batch_create(int32_t n, const ddf_params *ps, void *pop_f, void *pop_g, 
         delete b;
         return fail(DDF_ERR_HIP, "cannot create the capture stream");
     }
-    rc = apply_tiling(b, 512, 0, b->cap_stream);
+    rc = quiesce();
+    if (rc == DDF_OK) rc = apply_tiling(b, 512, 0, b->cap_stream);
     if (rc != DDF_OK) {
         (void)hipStreamDestroy(b->cap_stream);
         delete b;
@@ -395,6 +407,7 @@ int ddf_batch_create(int32_t n, const ddf_params *ps, void *pop_f, void *pop_g, 
 void ddf_batch_destroy(ddf_batch *b)
 {
     if (!b) return;
+    (void)quiesce();
     drop_graph(b);
     (void)hipStreamDestroy(b->cap_stream);
     delete b;
@@ -443,6 +456,8 @@ int ddf_batch_set_active(ddf_batch *b, const uint8_t *active)
     // an instance leaves and re-enters the step list in the natural slot order, so its
     // stored state stays readable as an even-step state while it is out
     if (b->step & 1) return fail(DDF_ERR_STATE, "set_active needs an even step count (natural slot order)");
+    int rc = quiesce();
+    if (rc != DDF_OK) return rc;
     for (int i = 0; i < b->n; ++i) b->active[i] = active[i] ? 1 : 0;
     return apply_tiling(b, b->bx_max, b->bpc, b->cap_stream);
 }
@@ -474,6 +489,8 @@ int ddf_batch_set_tiling(ddf_batch *b, int32_t bx_max, int32_t blocks_per_cu)
     for (int c : kBxCandidates) ok |= (c == bx_max);
     if (!ok) return fail(DDF_ERR_ARG, "bx_max must be 64, 128, 256 or 512");
     if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(DDF_ERR_ARG, "blocks_per_cu must lie in [0, 64]");
+    int rc = quiesce();
+    if (rc != DDF_OK) return rc;
     return apply_tiling(b, bx_max, blocks_per_cu, b->cap_stream);
 }
 
@@ -493,6 +510,10 @@ int ddf_batch_set_graph(ddf_batch *b, int32_t steps_per_graph)
     if (steps_per_graph < 0 || (steps_per_graph & 1)) return fail(DDF_ERR_ARG, "steps_per_graph must be even and >= 0");
     if (steps_per_graph > 0 && b->pulsatile)
         return fail(DDF_ERR_UNSUPPORTED, "time-dependent forces are stepped eagerly (no graph capture)");
+    if (b->captured_steps) {
+        int rc = quiesce();
+        if (rc != DDF_OK) return rc;
+    }
     drop_graph(b);
     b->graph_steps = steps_per_graph;
     return DDF_OK;

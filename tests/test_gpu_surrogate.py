@@ -155,3 +155,27 @@ def test_corrupted_network_falls_back_everywhere():
     assert fb.all()
     b.step(100)
     assert np.all(b.reduce()["nonfinite"] == 0)
+
+
+def test_batch_created_while_a_prediction_is_in_flight():
+    # Regression: a batch created right after a prediction whose outputs were dropped
+    # receives memory the allocator recycled while the prediction's kernels may still
+    # write it; the batch's setup must wait for them before uploading its tile lists.
+    say("case: batch created behind in-flight prediction kernels")
+    cases = held_out(16, lowest_re=16)
+    re, u = tensors(cases)
+    net, _ = S.load_weights(WEIGHTS, device=DEV)
+    S.predict_batch_fields(net, re, u, N, N)          # outputs dropped at once
+    b = batch_of(cases)
+    cold_init(b, len(cases))
+    b.step(200)
+    s = b.reduce()
+    assert np.all(s["nonfinite"] == 0)
+    torch.cuda.synchronize()
+    ref = batch_of(cases)
+    cold_init(ref, len(cases))
+    ref.step(200)
+    for i in range(len(cases)):
+        fa, ga = b.get_populations(i, raw=True)
+        fr, gr = ref.get_populations(i, raw=True)
+        assert torch.equal(fa, fr) and torch.equal(ga, gr), i
