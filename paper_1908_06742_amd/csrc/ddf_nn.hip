@@ -125,14 +125,148 @@ __global__ __launch_bounds__(64) void k_conv3x3_wgrad(const __bf16 *__restrict__
     }
 }
 
-// out[i] (= or +=) sum_c part[c][i], c = 0 .. nchunk-1 in order.
-__global__ void k_sum_chunks(const float *__restrict__ part, int64_t n, int nchunk, float *__restrict__ out, int accumulate)
+// LDS-staged weight gradient.  A workgroup of three wavefronts, one per kernel row
+// (dy = -1, 0, 1), walks a run of pixel blocks; a block is PB consecutive pixels of one
+// image row.  Per block it stages with 16-byte loads the output gradient dout[PB][32 CO_T]
+// and the three input rows in[y-1 .. y+1][x0-1 .. x0+PB] (zero outside the image); then
+// each wavefront contracts over the block's pixels for its three taps (dx = -1, 0, 1)
+// and its CO_T x CI_T output tiles of 32 x 32, so each staged value feeds several MFMAs.
+// The contraction runs over pixels, which NHWC keeps strided, so operands are gathered
+// from LDS as 8 single bf16 values per lane; rows are padded by 8 elements so that the
+// two half-waves (pixel offsets 0 and 8) read disjoint banks.
+// part[chunk][tap][co][ci] receives the chunk's sums (tap = 3 (dy + 1) + dx + 1).  The
+// workgroups of the first input-channel tile also sum the staged output gradient over
+// the chunk's pixels into bpart[chunk][co] (bias gradient), in a fixed order.
+template <int PB, int CO_T, int CI_T>
+__global__ __launch_bounds__(192) void k_wgrad_lds(const __bf16 *__restrict__ in, int N, int H, int W, int Cin,
+                                                   int in_cs, int in_co, const __bf16 *__restrict__ dout, int Cout,
+                                                   int d_cs, int blocks_per_chunk, float *__restrict__ part,
+                                                   float *__restrict__ bpart)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    constexpr int XS = 32 * CI_T + 8;
+    constexpr int DS = 32 * CO_T + 8;
+    __shared__ __attribute__((aligned(16))) __bf16 xs[3][PB + 2][XS];
+    __shared__ __attribute__((aligned(16))) __bf16 ds[PB][DS];
+    __shared__ float bred[192][8];
+    const int tid = threadIdx.x, lane = tid & 63, r = tid >> 6;
+    const int m = lane & 31, half = lane >> 5;
+    const int tiles_ci = Cin / (32 * CI_T);
+    const int ci0 = (blockIdx.x % tiles_ci) * 32 * CI_T, co0 = (blockIdx.x / tiles_ci) * 32 * CO_T;
+    const bool bias = bpart != nullptr && blockIdx.x % tiles_ci == 0;
+    float bsum[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) bsum[i] = 0.0f;
+    const int ck = blockIdx.y;
+    const int bpr = W / PB;
+    const int64_t nblocks = (int64_t)N * H * bpr;
+    const int64_t b0 = (int64_t)ck * blocks_per_chunk;
+    const int64_t b1 = b0 + blocks_per_chunk < nblocks ? b0 + blocks_per_chunk : nblocks;
+    f32x16 acc[3][CO_T][CI_T];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+        for (int a = 0; a < CO_T; ++a)
+#pragma unroll
+            for (int b = 0; b < CI_T; ++b)
+#pragma unroll
+                for (int j = 0; j < 16; ++j) acc[dx][a][b][j] = 0.0f;
+    for (int64_t blk = b0; blk < b1; ++blk) {
+        const int x0 = (int)(blk % bpr) * PB;
+        const int64_t row = blk / bpr;   // n * H + y
+        const int y = (int)(row % H);
+        constexpr int XV = 3 * (PB + 2) * 4 * CI_T;
+        for (int v = tid; v < XV; v += 192) {
+            const int c8 = v % (4 * CI_T), q = v / (4 * CI_T);
+            const int px = q % (PB + 2), rr = q / (PB + 2);
+            const int yy = y + rr - 1, xx = x0 + px - 1;
+            bf16x8 val = zero8();
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                val = load8(in + ((row + rr - 1) * W + xx) * in_cs + in_co + ci0 + 8 * c8);
+            *(bf16x8 *)&xs[rr][px][8 * c8] = val;
+        }
+        constexpr int DV = PB * 4 * CO_T;
+        // 192 is a multiple of 4 CO_T: a thread keeps one group of 8 channels
+        for (int v = tid; v < DV; v += 192) {
+            const int c8 = v % (4 * CO_T), px = v / (4 * CO_T);
+            const bf16x8 dv = load8(dout + (row * W + x0 + px) * d_cs + co0 + 8 * c8);
+            *(bf16x8 *)&ds[px][8 * c8] = dv;
+            if (bias) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) bsum[i] += (float)dv[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k0 = 0; k0 < PB; k0 += 16) {
+            const int kk = k0 + 8 * half;
+            bf16x8 a[CO_T];
+#pragma unroll
+            for (int t = 0; t < CO_T; ++t)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) a[t][i] = ds[kk + i][32 * t + m];
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+#pragma unroll
+                for (int u = 0; u < CI_T; ++u) {
+                    bf16x8 b;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) b[i] = xs[r][kk + i + dx][32 * u + m];
+#pragma unroll
+                    for (int t = 0; t < CO_T; ++t)
+                        acc[dx][t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[t], b, acc[dx][t][u], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (bias) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) bred[tid][i] = bsum[i];
+        __syncthreads();
+        if (tid < 32 * CO_T) {
+            const int c8 = tid >> 3, i = tid & 7;
+            float t = 0.0f;
+            for (int u = c8; u < 192; u += 4 * CO_T) t += bred[u][i];
+            bpart[(int64_t)ck * Cout + co0 + 8 * c8 + i] = t;
+        }
+    }
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+        float *o = part + (((int64_t)ck * 9 + 3 * r + dx) * Cout) * Cin;
+#pragma unroll
+        for (int t = 0; t < CO_T; ++t)
+#pragma unroll
+            for (int u = 0; u < CI_T; ++u)
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int co = co0 + 32 * t + 8 * (j >> 2) + 4 * half + (j & 3);
+                    o[(int64_t)co * Cin + ci0 + 32 * u + m] = acc[dx][t][u][j];
+                }
+    }
+}
+
+// out[i] (= or +=) sum_c part[c][i] over c = 0 .. nchunk-1, in a fixed order: in a block
+// of 32 elements x 8 chunk groups, thread (e, q) sums the chunks c = q, q + 8, ... of
+// element e in increasing c, then the eight group sums are added for q = 0 .. 7.
+__global__ __launch_bounds__(256) void k_sum_chunks(const float *__restrict__ part, int64_t n, int nchunk,
+                                                    float *__restrict__ out, int accumulate)
+{
+    __shared__ float red[8][32];
+    const int e = threadIdx.x & 31, q = threadIdx.x >> 5;
+    const int64_t i = (int64_t)blockIdx.x * 32 + e;
     float s = 0.0f;
-    for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * n + i];
-    out[i] = accumulate ? out[i] + s : s;
+    if (i < n) {
+#pragma unroll 8
+        for (int c = q; c < nchunk; c += 8) s += part[(int64_t)c * n + i];
+    }
+    red[q][e] = s;
+    __syncthreads();
+    if (q == 0 && i < n) {
+        float t = red[0][e];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) t += red[k][e];
+        out[i] = accumulate ? out[i] + t : t;
+    }
 }
 
 // Bias gradient partials: part[b][co] = sum of dout[p, co] over pixel block b (256 pixels).
@@ -343,6 +477,9 @@ __global__ void k_cavity_fields(const __bf16 *__restrict__ out, int o_cs, const 
 
 inline int blocks_for(int64_t n, int t = 256) { return (int)((n + t - 1) / t); }
 
+constexpr int64_t kWgradWaves = 8192;    // target single-wave workgroups of the gather kernel
+constexpr int64_t kWgradGroups = 768;    // target three-wave workgroups of the LDS-staged kernel
+
 int check_launch()
 {
     hipError_t e = hipGetLastError();
@@ -380,17 +517,76 @@ int ddf_nn_conv3x3(const void *in, int32_t N, int32_t H, int32_t W, int32_t Cin,
     return check_launch();
 }
 
+}  // extern "C"
+
+namespace {
+
+// How ddf_nn_conv3x3_wgrad splits its work; the workspace size follows from it.
+struct WgradPlan {
+    bool lds;              // LDS-staged kernel (rows of W % 16 == 0 pixels)
+    int pb, co_t, ci_t;    // its pixel block and tile multiples
+    int64_t nchunk;        // split-K chunks (partials)
+    int64_t per_chunk;     // pixel blocks (LDS kernel) or pixels (gather kernel) per chunk
+};
+
+WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout)
+{
+    WgradPlan P{};
+    const int64_t npix = (int64_t)N * H * W;
+    P.pb = W % 64 == 0 ? 64 : (W % 32 == 0 ? 32 : (W % 16 == 0 ? 16 : 0));
+    P.lds = P.pb > 0;
+    if (P.lds) {
+        P.co_t = Cout % 64 == 0 ? 2 : 1;
+        P.ci_t = Cin % 64 == 0 ? 2 : 1;
+        const int64_t groups = (int64_t)(Cin / (32 * P.ci_t)) * (Cout / (32 * P.co_t));
+        const int64_t nblocks = npix / P.pb;
+        int64_t nchunk = (kWgradGroups + groups - 1) / groups;
+        nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, nblocks));
+        P.per_chunk = (nblocks + nchunk - 1) / nchunk;
+        P.nchunk = (nblocks + P.per_chunk - 1) / P.per_chunk;
+    } else {
+        // gather kernel: about kWgradWaves single-wave workgroups, chunks of >= 256 pixels
+        const int64_t tiles = (int64_t)std::max(1, Cin / 32) * std::max(1, Cout / 32);
+        int64_t nchunk = (kWgradWaves + 9 * tiles - 1) / (9 * tiles);
+        nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, (npix + 255) / 256));
+        int64_t chunk = (npix + nchunk - 1) / nchunk;
+        chunk = (chunk + 15) / 16 * 16;
+        P.per_chunk = chunk;
+        P.nchunk = (npix + chunk - 1) / chunk;
+    }
+    return P;
+}
+
+template <int PB>
+int launch_wgrad_lds(const WgradPlan &P, const __bf16 *in, int N, int H, int W, int Cin, int in_cs, int in_co,
+                     const __bf16 *dout, int Cout, int d_cs, float *part, float *bpart, hipStream_t st)
+{
+    const dim3 grid((unsigned)((Cin / (32 * P.ci_t)) * (Cout / (32 * P.co_t))), (unsigned)P.nchunk);
+    const int bpc = (int)P.per_chunk;
+#define DDF_WGRAD_LAUNCH(CO, CI)                                                                                   \
+    hipLaunchKernelGGL((k_wgrad_lds<PB, CO, CI>), grid, dim3(192), 0, st, in, N, H, W, Cin, in_cs, in_co, dout, Cout, \
+                       d_cs, bpc, part, bpart)
+    if (P.co_t == 2 && P.ci_t == 2) DDF_WGRAD_LAUNCH(2, 2);
+    else if (P.co_t == 2) DDF_WGRAD_LAUNCH(2, 1);
+    else if (P.ci_t == 2) DDF_WGRAD_LAUNCH(1, 2);
+    else DDF_WGRAD_LAUNCH(1, 1);
+#undef DDF_WGRAD_LAUNCH
+    return DDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 size_t ddf_nn_wgrad_workspace_bytes(int32_t N, int32_t H, int32_t W, int32_t Cin, int32_t Cout, int32_t *chunk_out)
 {
     const int64_t npix = (int64_t)N * H * W;
-    // chunk: at least 512 pixels, at most 64 chunks
-    int64_t chunk = std::max<int64_t>(512, (npix + 63) / 64);
-    chunk = (chunk + 15) / 16 * 16;
-    const int64_t nchunk = (npix + chunk - 1) / chunk;
-    if (chunk_out) *chunk_out = (int32_t)chunk;
+    const WgradPlan P = wgrad_plan(N, H, W, Cin, Cout);
+    if (chunk_out) *chunk_out = (int32_t)(P.lds ? P.per_chunk * P.pb : P.per_chunk);
     const int64_t wsz = (int64_t)9 * Cout * Cin;
+    if (P.lds) return (size_t)(P.nchunk * (wsz + Cout)) * sizeof(float);
     const int64_t bsz = ((npix + 255) / 256) * Cout;
-    return (size_t)std::max(nchunk * wsz, bsz) * sizeof(float);
+    return (size_t)std::max(P.nchunk * wsz, bsz) * sizeof(float);
 }
 
 int ddf_nn_conv3x3_wgrad(const void *in, int32_t N, int32_t H, int32_t W, int32_t Cin, int32_t in_cs, int32_t in_co,
@@ -398,21 +594,39 @@ int ddf_nn_conv3x3_wgrad(const void *in, int32_t N, int32_t H, int32_t W, int32_
                          void *workspace, void *stream)
 {
     if (!in || !dout || !dw || !workspace) return fail(DDF_ERR_ARG, "wgrad: null pointer");
+    if (N <= 0 || H <= 0 || W <= 0) return fail(DDF_ERR_ARG, "wgrad: bad shape");
     if (Cin % 32 || Cout % 32) return fail(DDF_ERR_ARG, "wgrad: Cin and Cout must be multiples of 32");
+    if (Cout > 256) return fail(DDF_ERR_ARG, "wgrad: Cout must be at most 256");
+    if (((uintptr_t)in | (uintptr_t)dout) & 15) return fail(DDF_ERR_ARG, "wgrad: tensors must be 16-byte aligned");
+    if (in_cs % 8 || in_co % 8 || d_cs % 8 || in_cs < in_co + Cin || d_cs < Cout)
+        return fail(DDF_ERR_ARG, "wgrad: channel strides and offsets must be multiples of 8 and cover the channels");
     hipStream_t st = (hipStream_t)stream;
-    int32_t chunk;
-    ddf_nn_wgrad_workspace_bytes(N, H, W, Cin, Cout, &chunk);
+    const WgradPlan P = wgrad_plan(N, H, W, Cin, Cout);
     const int64_t npix = (int64_t)N * H * W;
-    const int nchunk = (int)((npix + chunk - 1) / chunk);
     float *part = (float *)workspace;
-    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3((Cin / 32) * (Cout / 32), 9, nchunk), dim3(64), 0, st,
-                       (const __bf16 *)in, N, H, W, Cin, in_cs, in_co, (const __bf16 *)dout, Cout, d_cs, chunk, part);
+    const __bf16 *ib = (const __bf16 *)in, *db16 = (const __bf16 *)dout;
     const int64_t wsz = (int64_t)9 * Cout * Cin;
-    hipLaunchKernelGGL(k_sum_chunks, dim3(blocks_for(wsz)), dim3(256), 0, st, part, wsz, nchunk, dw, accumulate);
+    if (P.lds) {
+        float *bpart = db ? part + P.nchunk * wsz : nullptr;
+        if (P.pb == 64) launch_wgrad_lds<64>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, st);
+        else if (P.pb == 32) launch_wgrad_lds<32>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, st);
+        else launch_wgrad_lds<16>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, st);
+        hipLaunchKernelGGL(k_sum_chunks, dim3(blocks_for(wsz, 32)), dim3(256), 0, st, part, wsz, (int)P.nchunk, dw,
+                           accumulate);
+        if (db)
+            hipLaunchKernelGGL(k_sum_chunks, dim3(blocks_for(Cout, 32)), dim3(256), 0, st, bpart, (int64_t)Cout,
+                               (int)P.nchunk, db, accumulate);
+        return check_launch();
+    }
+    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3((Cin / 32) * (Cout / 32), 9, (unsigned)P.nchunk), dim3(64), 0, st, ib, N, H,
+                       W, Cin, in_cs, in_co, db16, Cout, d_cs, (int)P.per_chunk, part);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(blocks_for(wsz, 32)), dim3(256), 0, st, part, wsz, (int)P.nchunk, dw,
+                       accumulate);
     if (db) {
         const int nb = (int)((npix + 255) / 256);
-        hipLaunchKernelGGL(k_bias_grad, dim3(nb), dim3(256), 0, st, (const __bf16 *)dout, (int)npix, Cout, d_cs, part);
-        hipLaunchKernelGGL(k_sum_chunks, dim3(blocks_for(Cout)), dim3(256), 0, st, part, (int64_t)Cout, nb, db, accumulate);
+        hipLaunchKernelGGL(k_bias_grad, dim3(nb), dim3(256), 0, st, db16, (int)npix, Cout, d_cs, part);
+        hipLaunchKernelGGL(k_sum_chunks, dim3(blocks_for(Cout, 32)), dim3(256), 0, st, part, (int64_t)Cout, nb, db,
+                           accumulate);
     }
     return check_launch();
 }

@@ -266,3 +266,32 @@ def test_cavity_input_channels():
         assert np.all(a[n, ..., 5:] == 0)
     bad = L.lib().ddf_nn_cavity_inputs(p(re), p(u), B, H, W, 4, 100.0, 5000.0, 0.1, p(x), s0())
     assert bad == L.DDF_ERR_ARG
+
+
+@pytest.mark.parametrize("B,H,W,Cin,Cout", [
+    (1, 4, 64, 64, 64),      # 64-pixel blocks, 2 x 2 tiles
+    (1, 3, 128, 96, 32),     # 64-pixel blocks, 1 x 1 tiles (96 input channels)
+    (2, 5, 32, 32, 64),      # 32-pixel blocks, 2 x 1 tiles
+    (1, 2, 16, 128, 256),    # 16-pixel blocks, 2 x 2 tiles over 4 x 2 tile groups
+    (2, 4, 8, 32, 32),       # rows of 8: the gather kernel
+])
+def test_weight_gradient_kernels(B, H, W, Cin, Cout):
+    r = np.random.default_rng(B * 1000 + H * 100 + W + Cin + Cout)
+    # input taken as channels [16, 16 + Cin) of a wider tensor
+    cs = Cin + 32
+    xt, x = bf(r.standard_normal((B, H, W, cs)))
+    dyt, dy = bf(r.standard_normal((B, H, W, Cout)))
+    _, rdw, rdb = U.conv3x3_backward(x[..., 16:16 + Cin], np.zeros((9, Cout, Cin)), dy)
+    ws = torch.empty(L.lib().ddf_nn_wgrad_workspace_bytes(B, H, W, Cin, Cout, None), dtype=torch.uint8, device=DEV)
+    dw = torch.full((9 * Cout * Cin,), 0.5, dtype=torch.float32, device=DEV)
+    db = torch.full((Cout,), 0.25, dtype=torch.float32, device=DEV)
+    L.check(L.lib().ddf_nn_conv3x3_wgrad(p(xt), B, H, W, Cin, cs, 16, p(dyt), Cout, Cout, p(dw), p(db), 1, p(ws), s0()))
+    assert rel(dw.cpu().numpy().reshape(9, Cout, Cin) - 0.5, rdw) < 1e-5
+    assert rel(db.cpu().numpy() - 0.25, rdb) < 1e-5
+    # deterministic: the same call gives the same bits
+    dw2 = torch.zeros_like(dw)
+    db2 = torch.zeros_like(db)
+    L.check(L.lib().ddf_nn_conv3x3_wgrad(p(xt), B, H, W, Cin, cs, 16, p(dyt), Cout, Cout, p(dw2), p(db2), 0, p(ws), s0()))
+    dw3 = torch.zeros_like(dw)
+    L.check(L.lib().ddf_nn_conv3x3_wgrad(p(xt), B, H, W, Cin, cs, 16, p(dyt), Cout, Cout, p(dw3), None, 0, p(ws), s0()))
+    assert torch.equal(dw2, dw3)
