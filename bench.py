@@ -243,6 +243,64 @@ def run_surrogate(count=16, cap=400_000):
             "steps_cold_over_warm": round(float(sc.sum() / sw.sum()), 2)}
 
 
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def unet_flops_per_sample(H=256, W=256, base=32, levels=4):
+    """Matrix-core FLOPs of one training sample (forward, data gradient, weight gradient)
+    of the surrogate U-Net as the kernels execute it (channels padded to 32)."""
+    from paper_1908_06742_amd.surrogate import layer_table, _pad
+
+    fwd = dgrad = 0
+    for name, ci, co, _ in layer_table(base, levels):
+        lvl = 0 if name == "head" else int(name[3])
+        cip = 32 if name == "enc0a" else _pad(ci)
+        f = 2.0 * 9 * cip * _pad(co) * (H >> lvl) * (W >> lvl)
+        fwd += f
+        if name != "enc0a":
+            dgrad += f
+    return fwd, fwd + dgrad + fwd
+
+
+def run_unet(batch=8, iters=50):
+    """One Adam training iteration of the surrogate U-Net on batch x 256^2 (forward, loss,
+    backward, Adam, BF16 weight casts), timed with HIP events; and the forward alone."""
+    import torch
+
+    from paper_1908_06742_amd.surrogate import UNet
+
+    H = W = 256
+    net = UNet(base=32, levels=4, device="cuda", seed=0)
+    re = torch.linspace(100, 5000, batch, device="cuda")
+    u = torch.full((batch,), 0.08, device="cuda")
+    tgt = torch.randn(batch * H * W * 4, device="cuda") * 0.1
+    for _ in range(3):
+        net.train_step(re, u, tgt, H, W, 1e-5)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(n):
+            fn()
+        e1.record(st)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    t_train = timed(lambda: net.train_step(re, u, tgt, H, W, 1e-5), iters)
+    net.inputs(re, u, H, W)
+    t_fwd = timed(lambda: net.forward(batch, H, W), iters)
+    f_fwd, f_train = unet_flops_per_sample(H, W)
+    tf_train = batch * f_train / (t_train * 1e-3) / 1e12
+    tf_fwd = batch * f_fwd / (t_fwd * 1e-3) / 1e12
+    return {"workload": f"surrogate U-Net (4 levels, base 32, BF16 MFMA), batch {batch} x 256^2",
+            "ms_per_train_iter": round(t_train, 3), "train_tflops": round(tf_train, 1),
+            "ms_per_forward": round(t_fwd, 3), "forward_tflops": round(tf_fwd, 1),
+            "peak_tflops": BF16_PEAK_TFLOPS, "train_frac": round(tf_train / BF16_PEAK_TFLOPS, 4),
+            "forward_frac": round(tf_fwd / BF16_PEAK_TFLOPS, 4)}
+
+
 def cpu_baseline(budget_s=12.0):
     """The FP64 oracle timed on the host cores on a bounded sample of the same
     workload: a 256 x 256 window of the vortex field run as a periodic lattice, in
@@ -312,6 +370,8 @@ def main():
     ap.add_argument("--oracle-timing", action="store_true",
                     help="also time the oracle single-threaded and on all threads on the small workloads")
     ap.add_argument("--variants", action="store_true", help="also time FP16/BF16/FP64 storage of the same field")
+    ap.add_argument("--only-extra", choices=["cavity", "batch", "surrogate", "unet"],
+                    help="run one extra line alone and print it (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -323,6 +383,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read_per_dispatch": 1 << 30, "copy_bytes_written_per_dispatch": 1 << 30}))
+        return
+    if args.only_extra:
+        fn = {"cavity": run_cavity, "batch": lambda: run_batch(args.batch_steps), "surrogate": run_surrogate,
+              "unet": run_unet}[args.only_extra]
+        print(json.dumps({args.only_extra: fn()}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the method's sharding "
@@ -381,6 +446,8 @@ def main():
         line["extras"]["batch256_f32"] = run_batch(args.batch_steps)
         print("[bench] extra: surrogate warm start vs cold start", file=sys.stderr, flush=True)
         line["extras"]["surrogate256_time_to_steady"] = run_surrogate()
+        print("[bench] extra: surrogate U-Net training step", file=sys.stderr, flush=True)
+        line["extras"]["unet256_train_b8"] = run_unet()
     if args.variants:
         var = []
         for st, L in (("f16", 8192), ("bf16", 8192), ("bf16sr", 8192), ("f64", 8192)):

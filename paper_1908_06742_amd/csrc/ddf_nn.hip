@@ -355,26 +355,143 @@ __global__ void k_slice(const __bf16 *__restrict__ src, int s_cs, int sc0, __bf1
     *d = (__bf16)(accumulate ? (float)*d + v : v);
 }
 
+// 8-channel (16-byte) forms of the elementwise kernels above, used when every channel
+// count, stride and offset is a multiple of 8 and the tensors are 16-byte aligned.
+__device__ __forceinline__ void store8(__bf16 *p, const bf16x8 &v) { *(bf16x8 *)p = v; }
+
+__global__ void k_relu_bwd8(__bf16 *__restrict__ g, const __bf16 *__restrict__ act, int64_t n8)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n8) return;
+    bf16x8 gv = load8(g + 8 * i);
+    const bf16x8 av = load8(act + 8 * i);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (!((float)av[k] > 0.0f)) gv[k] = (__bf16)0.0f;
+    store8(g + 8 * i, gv);
+}
+
+__global__ void k_pool2_8(const __bf16 *__restrict__ in, int N, int H, int W, int C, __bf16 *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int h = H / 2, w = W / 2, C8 = C / 8;
+    if (i >= (int64_t)N * h * w * C8) return;
+    const int c = 8 * (int)(i % C8);
+    const int64_t q = i / C8;
+    const int xo = q % w, yo = (q / w) % h, n = q / ((int64_t)w * h);
+    const __bf16 *b = in + ((int64_t)(n * H + 2 * yo) * W + 2 * xo) * C + c;
+    const bf16x8 a0 = load8(b), a1 = load8(b + C), a2 = load8(b + (int64_t)W * C), a3 = load8(b + (int64_t)W * C + C);
+    bf16x8 r;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r[k] = (__bf16)(0.25f * ((float)a0[k] + (float)a1[k] + (float)a2[k] + (float)a3[k]));
+    store8(out + q * C + c, r);
+}
+
+__global__ void k_pool2_bwd8(const __bf16 *__restrict__ dout, int N, int H, int W, int C, __bf16 *__restrict__ din,
+                             int accumulate)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int C8 = C / 8;
+    if (i >= (int64_t)N * H * W * C8) return;
+    const int c = 8 * (int)(i % C8);
+    const int64_t q = i / C8;
+    const int x = q % W, y = (q / W) % H, n = q / ((int64_t)W * H);
+    const bf16x8 d = load8(dout + ((int64_t)(n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c);
+    bf16x8 r = accumulate ? load8(din + q * C + c) : zero8();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float v = 0.25f * (float)d[k];
+        r[k] = (__bf16)(accumulate ? (float)r[k] + v : v);
+    }
+    store8(din + q * C + c, r);
+}
+
+__global__ void k_up2_8(const __bf16 *__restrict__ in, int N, int h, int w, int C, __bf16 *__restrict__ out,
+                        int out_cs, int oc0)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int H = 2 * h, W = 2 * w, C8 = C / 8;
+    if (i >= (int64_t)N * H * W * C8) return;
+    const int c = 8 * (int)(i % C8);
+    const int64_t q = i / C8;
+    const int x = q % W, y = (q / W) % H, n = q / ((int64_t)W * H);
+    store8(out + q * out_cs + oc0 + c, load8(in + ((int64_t)(n * h + y / 2) * w + x / 2) * C + c));
+}
+
+__global__ void k_up2_bwd8(const __bf16 *__restrict__ dout, int N, int h, int w, int C, int d_cs, int dc0,
+                           __bf16 *__restrict__ din)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int C8 = C / 8;
+    if (i >= (int64_t)N * h * w * C8) return;
+    const int c = 8 * (int)(i % C8);
+    const int64_t q = i / C8;
+    const int x = q % w, y = (q / w) % h, n = q / ((int64_t)w * h);
+    const int W = 2 * w;
+    const int64_t b = ((int64_t)(n * 2 * h + 2 * y) * W + 2 * x);
+    const bf16x8 a0 = load8(dout + b * d_cs + dc0 + c), a1 = load8(dout + (b + 1) * d_cs + dc0 + c);
+    const bf16x8 a2 = load8(dout + (b + W) * d_cs + dc0 + c), a3 = load8(dout + (b + W + 1) * d_cs + dc0 + c);
+    bf16x8 r;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r[k] = (__bf16)((float)a0[k] + (float)a1[k] + (float)a2[k] + (float)a3[k]);
+    store8(din + q * C + c, r);
+}
+
+__global__ void k_slice8(const __bf16 *__restrict__ src, int s_cs, int sc0, __bf16 *__restrict__ dst, int d_cs, int dc0,
+                         int64_t npix, int C, int accumulate)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int C8 = C / 8;
+    if (i >= npix * C8) return;
+    const int c = 8 * (int)(i % C8);
+    const int64_t p = i / C8;
+    const bf16x8 v = load8(src + p * s_cs + sc0 + c);
+    __bf16 *d = dst + p * d_cs + dc0 + c;
+    if (!accumulate) {
+        store8(d, v);
+        return;
+    }
+    bf16x8 r = load8(d);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r[k] = (__bf16)((float)r[k] + (float)v[k]);
+    store8(d, r);
+}
+
+inline bool al16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
 // Weighted MSE over the first 4 channels of out (channel stride o_cs): per-block FP64
 // partial of sum_c w_c (out_c - t_c)^2, and d out = 2 w_c (out_c - t_c) / npix (zero in
 // the padding channels).
 __global__ __launch_bounds__(256) void k_mse(const __bf16 *__restrict__ out, int o_cs, const float *__restrict__ target,
                                              int64_t npix, float w0, float w1, float w2, float w3,
-                                             __bf16 *__restrict__ dout, double *__restrict__ part)
+                                             __bf16 *__restrict__ dout, double *__restrict__ part, int vec)
 {
     __shared__ double sh[256];
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double acc = 0.0;
     if (p < npix) {
         const float wc[4] = {w0, w1, w2, w3};
-        for (int c = 0; c < o_cs; ++c) {
-            float g = 0.0f;
-            if (c < 4) {
-                const float d = (float)out[p * o_cs + c] - target[p * 4 + c];
+        if (vec) {   // 16-byte rows: the first vector carries the gradient, the rest zeros
+            bf16x8 g = zero8();
+            const bf16x8 o = load8(out + p * o_cs);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float d = (float)o[c] - target[p * 4 + c];
                 acc += (double)wc[c] * (double)d * (double)d;
-                g = 2.0f * wc[c] * d / (float)npix;
+                g[c] = (__bf16)(2.0f * wc[c] * d / (float)npix);
             }
-            dout[p * o_cs + c] = (__bf16)g;
+            store8(dout + p * o_cs, g);
+            for (int c = 8; c < o_cs; c += 8) store8(dout + p * o_cs + c, zero8());
+        } else {
+            for (int c = 0; c < o_cs; ++c) {
+                float g = 0.0f;
+                if (c < 4) {
+                    const float d = (float)out[p * o_cs + c] - target[p * 4 + c];
+                    acc += (double)wc[c] * (double)d * (double)d;
+                    g = 2.0f * wc[c] * d / (float)npix;
+                }
+                dout[p * o_cs + c] = (__bf16)g;
+            }
         }
     }
     sh[threadIdx.x] = acc;
@@ -386,12 +503,20 @@ __global__ __launch_bounds__(256) void k_mse(const __bf16 *__restrict__ out, int
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void k_sum_f64(const double *__restrict__ part, int n, double *__restrict__ out)
+// out[0] = sum of part[0 .. n): thread t sums part[t], part[t + 256], ... in order, then a
+// fixed-order tree over the 256 thread sums (deterministic).
+__global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ part, int n, double *__restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double sh[256];
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    out[0] = s;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
 }
 
 // Adam with bias correction on FP32 master weights.
@@ -634,16 +759,24 @@ int ddf_nn_conv3x3_wgrad(const void *in, int32_t N, int32_t H, int32_t W, int32_
 int ddf_nn_relu_bwd(void *grad, const void *act, int64_t n, void *stream)
 {
     if (!grad || !act) return fail(DDF_ERR_ARG, "relu_bwd: null pointer");
-    hipLaunchKernelGGL(k_relu_bwd, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, (__bf16 *)grad,
-                       (const __bf16 *)act, n);
+    if (n % 8 == 0 && al16(grad) && al16(act))
+        hipLaunchKernelGGL(k_relu_bwd8, dim3(blocks_for(n / 8)), dim3(256), 0, (hipStream_t)stream, (__bf16 *)grad,
+                           (const __bf16 *)act, n / 8);
+    else
+        hipLaunchKernelGGL(k_relu_bwd, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, (__bf16 *)grad,
+                           (const __bf16 *)act, n);
     return check_launch();
 }
 
 int ddf_nn_pool2(const void *in, int32_t N, int32_t H, int32_t W, int32_t C, void *out, void *stream)
 {
     if (H % 2 || W % 2) return fail(DDF_ERR_ARG, "pool2: H and W must be even");
-    hipLaunchKernelGGL(k_pool2, dim3(blocks_for((int64_t)N * H * W * C / 4)), dim3(256), 0, (hipStream_t)stream,
-                       (const __bf16 *)in, N, H, W, C, (__bf16 *)out);
+    if (C % 8 == 0 && al16(in) && al16(out))
+        hipLaunchKernelGGL(k_pool2_8, dim3(blocks_for((int64_t)N * H * W * C / 32)), dim3(256), 0, (hipStream_t)stream,
+                           (const __bf16 *)in, N, H, W, C, (__bf16 *)out);
+    else
+        hipLaunchKernelGGL(k_pool2, dim3(blocks_for((int64_t)N * H * W * C / 4)), dim3(256), 0, (hipStream_t)stream,
+                           (const __bf16 *)in, N, H, W, C, (__bf16 *)out);
     return check_launch();
 }
 
@@ -651,32 +784,48 @@ int ddf_nn_pool2_bwd(const void *dout, int32_t N, int32_t H, int32_t W, int32_t 
                      void *stream)
 {
     if (H % 2 || W % 2) return fail(DDF_ERR_ARG, "pool2_bwd: H and W must be even");
-    hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks_for((int64_t)N * H * W * C)), dim3(256), 0, (hipStream_t)stream,
-                       (const __bf16 *)dout, N, H, W, C, (__bf16 *)din, accumulate);
+    if (C % 8 == 0 && al16(dout) && al16(din))
+        hipLaunchKernelGGL(k_pool2_bwd8, dim3(blocks_for((int64_t)N * H * W * C / 8)), dim3(256), 0,
+                           (hipStream_t)stream, (const __bf16 *)dout, N, H, W, C, (__bf16 *)din, accumulate);
+    else
+        hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks_for((int64_t)N * H * W * C)), dim3(256), 0, (hipStream_t)stream,
+                           (const __bf16 *)dout, N, H, W, C, (__bf16 *)din, accumulate);
     return check_launch();
 }
 
 int ddf_nn_up2(const void *in, int32_t N, int32_t h, int32_t w, int32_t C, void *out, int32_t out_cs, int32_t out_co,
                void *stream)
 {
-    hipLaunchKernelGGL(k_up2, dim3(blocks_for((int64_t)N * 4 * h * w * C)), dim3(256), 0, (hipStream_t)stream,
-                       (const __bf16 *)in, N, h, w, C, (__bf16 *)out, out_cs, out_co);
+    if (C % 8 == 0 && out_cs % 8 == 0 && out_co % 8 == 0 && al16(in) && al16(out))
+        hipLaunchKernelGGL(k_up2_8, dim3(blocks_for((int64_t)N * 4 * h * w * C / 8)), dim3(256), 0, (hipStream_t)stream,
+                           (const __bf16 *)in, N, h, w, C, (__bf16 *)out, out_cs, out_co);
+    else
+        hipLaunchKernelGGL(k_up2, dim3(blocks_for((int64_t)N * 4 * h * w * C)), dim3(256), 0, (hipStream_t)stream,
+                           (const __bf16 *)in, N, h, w, C, (__bf16 *)out, out_cs, out_co);
     return check_launch();
 }
 
 int ddf_nn_up2_bwd(const void *dout, int32_t N, int32_t h, int32_t w, int32_t C, int32_t d_cs, int32_t d_co, void *din,
                    void *stream)
 {
-    hipLaunchKernelGGL(k_up2_bwd, dim3(blocks_for((int64_t)N * h * w * C)), dim3(256), 0, (hipStream_t)stream,
-                       (const __bf16 *)dout, N, h, w, C, d_cs, d_co, (__bf16 *)din);
+    if (C % 8 == 0 && d_cs % 8 == 0 && d_co % 8 == 0 && al16(dout) && al16(din))
+        hipLaunchKernelGGL(k_up2_bwd8, dim3(blocks_for((int64_t)N * h * w * C / 8)), dim3(256), 0, (hipStream_t)stream,
+                           (const __bf16 *)dout, N, h, w, C, d_cs, d_co, (__bf16 *)din);
+    else
+        hipLaunchKernelGGL(k_up2_bwd, dim3(blocks_for((int64_t)N * h * w * C)), dim3(256), 0, (hipStream_t)stream,
+                           (const __bf16 *)dout, N, h, w, C, d_cs, d_co, (__bf16 *)din);
     return check_launch();
 }
 
 int ddf_nn_slice(const void *src, int32_t s_cs, int32_t s_co, void *dst, int32_t d_cs, int32_t d_co, int64_t npix,
                  int32_t C, int32_t accumulate, void *stream)
 {
-    hipLaunchKernelGGL(k_slice, dim3(blocks_for(npix * C)), dim3(256), 0, (hipStream_t)stream, (const __bf16 *)src, s_cs,
-                       s_co, (__bf16 *)dst, d_cs, d_co, npix, C, accumulate);
+    if (C % 8 == 0 && s_cs % 8 == 0 && s_co % 8 == 0 && d_cs % 8 == 0 && d_co % 8 == 0 && al16(src) && al16(dst))
+        hipLaunchKernelGGL(k_slice8, dim3(blocks_for(npix * C / 8)), dim3(256), 0, (hipStream_t)stream,
+                           (const __bf16 *)src, s_cs, s_co, (__bf16 *)dst, d_cs, d_co, npix, C, accumulate);
+    else
+        hipLaunchKernelGGL(k_slice, dim3(blocks_for(npix * C)), dim3(256), 0, (hipStream_t)stream, (const __bf16 *)src,
+                           s_cs, s_co, (__bf16 *)dst, d_cs, d_co, npix, C, accumulate);
     return check_launch();
 }
 
@@ -689,9 +838,10 @@ int ddf_nn_mse(const void *out, int32_t o_cs, const float *target, int64_t npix,
     hipStream_t st = (hipStream_t)stream;
     const int nb = (int)((npix + 255) / 256);
     double *part = (double *)workspace;
+    const int vec = o_cs % 8 == 0 && al16(out) && al16(dout);
     hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, (const __bf16 *)out, o_cs, target, npix, weights4[0],
-                       weights4[1], weights4[2], weights4[3], (__bf16 *)dout, part);
-    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(64), 0, st, part, nb, loss_dev);
+                       weights4[1], weights4[2], weights4[3], (__bf16 *)dout, part, vec);
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, st, part, nb, loss_dev);
     return check_launch();
 }
 

@@ -295,3 +295,34 @@ def test_weight_gradient_kernels(B, H, W, Cin, Cout):
     dw3 = torch.zeros_like(dw)
     L.check(L.lib().ddf_nn_conv3x3_wgrad(p(xt), B, H, W, Cin, cs, 16, p(dyt), Cout, Cout, p(dw3), None, 0, p(ws), s0()))
     assert torch.equal(dw2, dw3)
+
+
+def test_elementwise_kernels_with_unaligned_channel_counts():
+    # 12 channels: the one-element-per-thread forms of pooling, upsampling and slices
+    r = np.random.default_rng(21)
+    B, H, W, C = 2, 6, 8, 12
+    xt, x = bf(r.standard_normal((B, H, W, C)))
+    pooled = torch.empty(B * H * W * C // 4, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_pool2(p(xt), B, H, W, C, p(pooled), s0()))
+    pq = np_of(pooled, (B, H // 2, W // 2, C))
+    assert rel(pq, U.pool2(x)) < 8e-3
+    up = torch.zeros(B * H * W * 20, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_up2(p(pooled), B, H // 2, W // 2, C, p(up), 20, 4, s0()))
+    assert np.array_equal(np_of(up, (B, H, W, 20))[..., 4:16], U.up2(pq))
+    gt, g = bf(r.standard_normal((B, H, W, 20)))
+    din = torch.empty(B * H * W * C // 4, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_up2_bwd(p(gt), B, H // 2, W // 2, C, 20, 4, p(din), s0()))
+    assert rel(np_of(din, pq.shape), U.up2_backward(g[..., 4:16])) < 8e-3
+    dp = torch.zeros(B * H * W * C, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_pool2_bwd(p(din), B, H, W, C, p(dp), 0, s0()))
+    assert rel(np_of(dp, x.shape), U.pool2_backward(np_of(din, pq.shape))) < 8e-3
+    dst, dq = bf(r.standard_normal((B, H, W, 20)))
+    L.check(L.lib().ddf_nn_slice(p(xt), C, 0, p(dst), 20, 3, B * H * W, C, 1, s0()))
+    want = dq.copy()
+    want[..., 3:15] += x
+    assert rel(np_of(dst, (B, H, W, 20))[..., 3:15], want[..., 3:15]) < 8e-3
+    gg = xt.clone()
+    L.check(L.lib().ddf_nn_relu_bwd(p(gg), p(xt), gg.numel() - 3, s0()))
+    got = np_of(gg, x.shape).reshape(-1)
+    ref = np.where(x > 0, x, 0.0).reshape(-1)
+    assert np.array_equal(got[:-3], ref[:-3]) and np.array_equal(got[-3:], x.reshape(-1)[-3:])
