@@ -36,19 +36,19 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(nodes):
+def measured_traffic(nodes, tile_width):
     """HBM bytes per step launch from the committed rocprofv3 counter summary, or None
-    when the kernel sources changed since the counters were taken."""
+    when the kernel sources or the tile width changed since the counters were taken."""
     try:
         d = json.load(open(COUNTERS_FILE))
     except (OSError, ValueError):
         return None
-    if d.get("kernel_hash") != kernel_hash() or d.get("nodes") != nodes:
+    if d.get("kernel_hash") != kernel_hash() or d.get("nodes") != nodes or d.get("tile_width") != tile_width:
         return None
     return d.get("bytes_per_launch")
 
 
-def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP):
+def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=None):
     import numpy as np
     import torch
 
@@ -59,6 +59,9 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP):
     pr = W.vortex_problem(L, storage=storage)
     fields = vf.eval_grid(np.arange(L), np.arange(L), device="cuda")
     lat = Lattice(pr, device="cuda").init(*fields)
+    if tile_width:
+        lat.set_tile_width(tile_width)
+    tile_width = lat.tile_width
     del fields
     out = torch.empty((16, L, L), dtype=torch.float32, device="cuda")
     names = ["rho", "ux", "uy", "phi", "Sxx", "Syy", "Sxy", "wz"]
@@ -98,6 +101,7 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP):
         "ms_per_step": 1e3 * dt / steps,
         "kernel_ms": kern_ms,
         "stats": stats,
+        "tile_width": tile_width,
     }
 
 
@@ -371,6 +375,7 @@ def main():
     ap.add_argument("--oracle-timing", action="store_true",
                     help="also time the oracle single-threaded and on all threads on the small workloads")
     ap.add_argument("--variants", action="store_true", help="also time FP16/BF16/FP64 storage of the same field")
+    ap.add_argument("--tile-width", type=int, default=None, help="tile width of the single-lattice kernels")
     ap.add_argument("--only-extra", choices=["cavity", "batch", "surrogate", "unet"],
                     help="run one extra line alone and print it (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -399,11 +404,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     print(f"[bench] {args.size}^2 {args.storage}: warmup {args.warmup}, timed {args.steps} steps "
           f"x {LB_STEPS_PER_STEP} LB steps", file=sys.stderr, flush=True)
-    r = run_gpu(args.size, args.storage, args.steps, args.warmup)
+    r = run_gpu(args.size, args.storage, args.steps, args.warmup, tile_width=args.tile_width)
     nodes = r["nodes"]
     bpn = BYTES_PER_NODE[args.storage]
     achieved = bpn * nodes / (r["kernel_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic(nodes) if args.storage == "f32" and args.size == 8192 else None
+    traffic = measured_traffic(nodes, r["tile_width"]) if args.storage == "f32" and args.size == 8192 else None
     cgbs = copy_gbs()
     line = {
         "metric": "MLUPS (fluid+scalar D2Q9 node-updates per second / 1e6)",
@@ -435,6 +440,7 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": bpn * nodes,
             "kernel_ms_per_launch": round(r["kernel_ms"], 4),
+            "tile_width": r["tile_width"],
             "copy_gbs": round(cgbs, 1),
             "frac_of_copy": round(achieved / cgbs, 4),
         },

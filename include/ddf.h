@@ -163,6 +163,20 @@ int ddf_get_populations(ddf_handle *h, void *f, void *g, int32_t dtype, void *st
 /* Inverse of ddf_get_populations; the step counter becomes `step`. */
 int ddf_set_populations(ddf_handle *h, const void *f, const void *g, int32_t dtype, int64_t step, void *stream);
 
+/* Tile shape of every kernel of this lattice: tiles are min(bx_max, row length rounded
+ * up to a power of two) nodes wide and 512 / width rows tall, one workgroup each
+ * (bx_max = 64, 128, 256 or 512; DDF_ERR_ARG otherwise).  Results do not depend on it.
+ * The default is 128 for 8- and 4-byte storage and 64 for 2-byte storage. */
+int ddf_set_tile_width(ddf_handle *h, int32_t bx_max);
+int32_t ddf_get_tile_width(const ddf_handle *h);
+/* ddf_step replays runs of steps_per_graph steps (even; default 100, 0 = always launch
+ * eagerly) captured once into a hipGraph; the remainder and an odd start launch
+ * eagerly.  Lattices with a time-dependent force or stochastic rounding always step
+ * eagerly (their kernels take the time index as an argument): DDF_ERR_UNSUPPORTED for
+ * steps_per_graph > 0.  Changing the tiling or the run length drops the captured graph
+ * (after waiting for the device). */
+int ddf_set_graph(ddf_handle *h, int32_t steps_per_graph);
+
 int64_t ddf_step_count(const ddf_handle *h);
 const char *ddf_last_error(void);
 

@@ -10,41 +10,90 @@ struct ddf_handle {
     ddf_params p;
     void *f, *g, *ws;
     Geom G;
+    int tile_width;
     int nblocks;
     int64_t step;
     int64_t snap_step;
     bool snap_valid;
     bool initialised;
     PhysPair P;
+    // runs of graph_steps steps are captured once into a hipGraph on cap_stream and
+    // replayed on the caller's stream
+    hipStream_t cap_stream;
+    hipGraphExec_t graph_exec;
+    int graph_steps;       // even; 0 = always launch eagerly
+    int captured_steps;    // steps of the instantiated graph, 0 = none
 };
 
 namespace {
 
 template <class S, int SC, bool W, bool FO>
-void launch_step_parity(ddf_handle *h, hipStream_t st, bool odd)
+void launch_step_parity(ddf_handle *h, hipStream_t st, bool odd, int64_t t)
 {
     const auto &P = h->P.of<S>();
     if (odd)
         hipLaunchKernelGGL((k_step<S, SC, W, FO, true>), dim3(h->nblocks), dim3(kThreads), 0, st, (S *)h->f, (S *)h->g,
-                           h->G, P, h->step);
+                           h->G, P, t);
     else
         hipLaunchKernelGGL((k_step<S, SC, W, FO, false>), dim3(h->nblocks), dim3(kThreads), 0, st, (S *)h->f, (S *)h->g,
-                           h->G, P, h->step);
+                           h->G, P, t);
 }
 
 template <class S, int SC>
-void launch_step(ddf_handle *h, hipStream_t st)
+void launch_step(ddf_handle *h, hipStream_t st, int64_t t)
 {
-    const bool odd = (h->step & 1) != 0;
+    const bool odd = (t & 1) != 0;
     const bool w = has_walls(h->p);
     const bool fo = h->p.force_kind != DDF_FORCE_NONE;
     if (w) {
-        if (fo) launch_step_parity<S, SC, true, true>(h, st, odd);
-        else launch_step_parity<S, SC, true, false>(h, st, odd);
+        if (fo) launch_step_parity<S, SC, true, true>(h, st, odd, t);
+        else launch_step_parity<S, SC, true, false>(h, st, odd, t);
     } else {
-        if (fo) launch_step_parity<S, SC, false, true>(h, st, odd);
-        else launch_step_parity<S, SC, false, false>(h, st, odd);
+        if (fo) launch_step_parity<S, SC, false, true>(h, st, odd, t);
+        else launch_step_parity<S, SC, false, false>(h, st, odd, t);
     }
+}
+
+// One step of time index t (its parity selects the streaming direction).
+void launch_one(ddf_handle *h, hipStream_t st, int64_t t)
+{
+    with_storage(h->p.storage, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        switch (h->p.scalar_model) {
+        case DDF_SCALAR_SRT: launch_step<S, DDF_SCALAR_SRT>(h, st, t); break;
+        case DDF_SCALAR_CASCADED:
+        case DDF_SCALAR_CENTRAL: launch_step<S, DDF_SCALAR_CENTRAL>(h, st, t); break;
+        default: launch_step<S, DDF_SCALAR_MRT>(h, st, t);
+        }
+        return 0;
+    });
+}
+
+// Kernels take the time index as an argument, which a captured graph freezes: lattices
+// whose step depends on it (a time-dependent force, stochastic rounding keys) run eagerly.
+bool graph_capable(const ddf_params &p) { return p.force_kind != DDF_FORCE_PULSATILE && p.storage != DDF_BF16_SR; }
+
+void drop_graph(ddf_handle *h)
+{
+    if (h->captured_steps) {
+        (void)hipGraphExecDestroy(h->graph_exec);
+        h->captured_steps = 0;
+    }
+}
+
+int capture_graph(ddf_handle *h)
+{
+    drop_graph(h);
+    if (!h->cap_stream) DDF_HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph;
+    DDF_HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < h->graph_steps; ++k) launch_one(h, h->cap_stream, k);   // starts at an even step
+    DDF_HIP_TRY(hipStreamEndCapture(h->cap_stream, &graph));
+    hipError_t e = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(DDF_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    h->captured_steps = h->graph_steps;
+    return DDF_OK;
 }
 
 }  // namespace
@@ -60,8 +109,23 @@ size_t ddf_population_bytes(const ddf_params *p) { return p ? population_bytes(p
 size_t ddf_workspace_bytes(const ddf_params *p)
 {
     if (!p || validate(p) != DDF_OK) return 0;
-    const Geom G = make_geom(*p);
-    return snap_bytes(p) + align256((size_t)grid_blocks(G) * RS_N * sizeof(double)) + 256;
+    // reduction partials for the largest block count any tile width gives
+    int blocks = 0;
+    for (int bx : {64, 128, 256, 512}) blocks = std::max(blocks, grid_blocks(make_geom(*p, bx)));
+    return snap_bytes(p) + align256((size_t)blocks * RS_N * sizeof(double)) + 256;
+}
+
+int ddf_set_tile_width(ddf_handle *h, int32_t bx_max)
+{
+    if (!h) return fail(DDF_ERR_ARG, "handle is NULL");
+    if (bx_max != 64 && bx_max != 128 && bx_max != 256 && bx_max != 512)
+        return fail(DDF_ERR_ARG, "tile width must be 64, 128, 256 or 512");
+    if (h->captured_steps) DDF_HIP_TRY(hipDeviceSynchronize());   // a replay may still be running
+    drop_graph(h);
+    h->tile_width = bx_max;
+    h->G = make_geom(h->p, bx_max);
+    h->nblocks = grid_blocks(h->G);
+    return DDF_OK;
 }
 
 int ddf_create(const ddf_params *p, void *pop_f, void *pop_g, void *workspace, ddf_handle **out)
@@ -78,7 +142,8 @@ int ddf_create(const ddf_params *p, void *pop_f, void *pop_g, void *workspace, d
     h->f = pop_f;
     h->g = pop_g;
     h->ws = workspace;
-    h->G = make_geom(*p);
+    h->tile_width = default_tile_width(p->storage);
+    h->G = make_geom(*p, h->tile_width);
     h->nblocks = grid_blocks(h->G);
     h->step = 0;
     h->snap_step = 0;
@@ -86,11 +151,35 @@ int ddf_create(const ddf_params *p, void *pop_f, void *pop_g, void *workspace, d
     h->initialised = false;
     h->P.d = make_phys<double>(*p);
     h->P.f = make_phys<float>(*p);
+    h->captured_steps = 0;
+    h->graph_steps = graph_capable(*p) ? 100 : 0;
+    h->cap_stream = nullptr;   // created at the first capture
     *out = h;
     return DDF_OK;
 }
 
-void ddf_destroy(ddf_handle *h) { delete h; }
+void ddf_destroy(ddf_handle *h)
+{
+    if (!h) return;
+    if (h->captured_steps) (void)hipDeviceSynchronize();   // a replay may still be running
+    drop_graph(h);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    delete h;
+}
+
+int ddf_set_graph(ddf_handle *h, int32_t steps_per_graph)
+{
+    if (!h) return fail(DDF_ERR_ARG, "handle is NULL");
+    if (steps_per_graph < 0 || (steps_per_graph & 1)) return fail(DDF_ERR_ARG, "steps_per_graph must be even and >= 0");
+    if (steps_per_graph > 0 && !graph_capable(h->p))
+        return fail(DDF_ERR_UNSUPPORTED, "time-dependent forces and stochastic rounding step eagerly (no graph capture)");
+    if (h->captured_steps) DDF_HIP_TRY(hipDeviceSynchronize());
+    drop_graph(h);
+    h->graph_steps = steps_per_graph;
+    return DDF_OK;
+}
+
+int32_t ddf_get_tile_width(const ddf_handle *h) { return h ? h->tile_width : 0; }
 
 int64_t ddf_step_count(const ddf_handle *h) { return h ? h->step : -1; }
 
@@ -121,17 +210,25 @@ int ddf_step(ddf_handle *h, int64_t nsteps, void *stream)
     if (nsteps < 0) return fail(DDF_ERR_ARG, "nsteps < 0");
     if (!h->initialised) return fail(DDF_ERR_STATE, "step before init or set_populations");
     hipStream_t st = (hipStream_t)stream;
-    for (int64_t i = 0; i < nsteps; ++i) {
-        with_storage(h->p.storage, [&](auto *tag) {
-            using S = std::remove_pointer_t<decltype(tag)>;
-            switch (h->p.scalar_model) {
-            case DDF_SCALAR_SRT: launch_step<S, DDF_SCALAR_SRT>(h, st); break;
-            case DDF_SCALAR_CASCADED:
-            case DDF_SCALAR_CENTRAL: launch_step<S, DDF_SCALAR_CENTRAL>(h, st); break;
-            default: launch_step<S, DDF_SCALAR_MRT>(h, st);
-            }
-            return 0;
-        });
+    int64_t left = nsteps;
+    if (h->graph_steps > 0 && left >= h->graph_steps + (h->step & 1)) {
+        if (h->step & 1) {   // replays start at an even step
+            launch_one(h, st, h->step);
+            h->step++;
+            left--;
+        }
+        if (h->captured_steps != h->graph_steps) {
+            int rc = capture_graph(h);
+            if (rc != DDF_OK) return rc;
+        }
+        while (left >= h->graph_steps) {
+            DDF_HIP_TRY(hipGraphLaunch(h->graph_exec, st));
+            h->step += h->graph_steps;
+            left -= h->graph_steps;
+        }
+    }
+    for (; left > 0; --left) {
+        launch_one(h, st, h->step);
         h->step++;
     }
     DDF_HIP_TRY(hipGetLastError());

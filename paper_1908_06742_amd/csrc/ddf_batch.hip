@@ -381,7 +381,9 @@ int ddf_batch_create(int32_t n, const ddf_params *ps, void *pop_f, void *pop_g, 
     b->snap_valid = false;
     b->initialised = false;
     b->captured_steps = 0;
-    b->graph_steps = b->pulsatile ? 0 : 100;
+    // kernels take the time index as an argument, which a captured graph freezes: a
+    // time-dependent force or stochastic rounding keys need eager launches
+    b->graph_steps = (b->pulsatile || b->storage == DDF_BF16_SR) ? 0 : 100;
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
@@ -508,8 +510,8 @@ int ddf_batch_set_graph(ddf_batch *b, int32_t steps_per_graph)
 {
     if (!b) return fail(DDF_ERR_ARG, "batch is NULL");
     if (steps_per_graph < 0 || (steps_per_graph & 1)) return fail(DDF_ERR_ARG, "steps_per_graph must be even and >= 0");
-    if (steps_per_graph > 0 && b->pulsatile)
-        return fail(DDF_ERR_UNSUPPORTED, "time-dependent forces are stepped eagerly (no graph capture)");
+    if (steps_per_graph > 0 && (b->pulsatile || b->storage == DDF_BF16_SR))
+        return fail(DDF_ERR_UNSUPPORTED, "time-dependent forces and stochastic rounding step eagerly (no graph capture)");
     if (b->captured_steps) {
         int rc = quiesce();
         if (rc != DDF_OK) return rc;

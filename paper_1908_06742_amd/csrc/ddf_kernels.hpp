@@ -427,6 +427,10 @@ inline int64_t pitch_of(const ddf_params *p) { return ((int64_t)p->nx + 63) / 64
 
 inline size_t storage_size(int storage) { return storage == DDF_F64 ? 8 : (storage == DDF_F32 ? 4 : 2); }
 
+// Single-lattice tile width by storage size (measured on the 8192^2 field: 128-wide
+// tiles for 8- and 4-byte storage, 64-wide for 2-byte storage).
+inline int default_tile_width(int storage) { return storage_size(storage) == 2 ? 64 : 128; }
+
 // Elements per direction plane: pitch * ny, plus 256 KiB + 256 B for planes of 16 MiB or more.
 inline int64_t plane_of(const ddf_params *p)
 {

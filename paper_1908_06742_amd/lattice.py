@@ -74,6 +74,20 @@ class Lattice:
         self._keep = fields  # alive until the stream has consumed them
         return self
 
+    def set_tile_width(self, bx_max):
+        """Tile width of this lattice's kernels (64, 128, 256 or 512); results do not change."""
+        L.check(L.lib().ddf_set_tile_width(self._h, int(bx_max)))
+        return self
+
+    @property
+    def tile_width(self):
+        return int(L.lib().ddf_get_tile_width(self._h))
+
+    def set_graph(self, steps_per_graph):
+        """Steps per captured hipGraph replay (even; 0 = eager launches)."""
+        L.check(L.lib().ddf_set_graph(self._h, int(steps_per_graph)))
+        return self
+
     def step(self, nsteps=1):
         L.check(L.lib().ddf_step(self._h, int(nsteps), _stream_ptr(self.stream)))
         return self

@@ -3,7 +3,7 @@
 Usage (each database from its own rocprofv3 run; see profiles/*.md for the commands):
   python -m paper_1908_06742_amd.profiling trace <run_results.db>
   python -m paper_1908_06742_amd.profiling counters <fetch.db> <write.db> <copy_fetch.db> <copy_write.db> \
-      --kernel k_step --nodes N --bytes-per-node B --out profiles/<name>_counters.json
+      --kernel k_step --nodes N --bytes-per-node B --tile-width T --out profiles/<name>_counters.json
 
 FETCH_SIZE and WRITE_SIZE are reported by rocprofv3 in KiB per dispatch.  Each is
 scaled by the ratio of the true byte count of a plain 1 GiB device copy to what the
@@ -73,7 +73,8 @@ def cmd_counters(args):
         import os
         sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
         import bench
-        json.dump({"kernel_hash": bench.kernel_hash(), "nodes": args.nodes, "bytes_per_launch": mean_total,
+        json.dump({"kernel_hash": bench.kernel_hash(), "nodes": args.nodes, "tile_width": args.tile_width,
+                   "bytes_per_launch": mean_total,
                    "algorithmic_bytes_per_launch": algo, "fetch_scale": f_scale, "write_scale": w_scale,
                    "per_parity": rows}, open(args.out, "w"), indent=1)
         print(f"wrote {args.out}")
@@ -93,6 +94,7 @@ def main(argv=None):
     c.add_argument("--kernel", default="k_step")
     c.add_argument("--nodes", type=int, required=True)
     c.add_argument("--bytes-per-node", type=int, required=True)
+    c.add_argument("--tile-width", type=int, required=True, help="tile width of the profiled lattice")
     c.add_argument("--out")
     args = ap.parse_args(argv)
     {"trace": cmd_trace, "counters": cmd_counters}[args.cmd](args)

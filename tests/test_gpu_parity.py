@@ -344,3 +344,48 @@ def test_bf16sr_runs_are_reproducible_and_differ_from_rne():
     fc, gc = c.get_populations(raw=True)
     assert torch.equal(fa.view(torch.int16), fb.view(torch.int16)) and torch.equal(ga.view(torch.int16), gb.view(torch.int16))
     assert not torch.equal(ga.view(torch.int16), gc.view(torch.int16))
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_single_lattice_graph_replays_equal_eager_steps(storage):
+    say(f"case: single-lattice graph replay {storage}")
+    pr = W.cavity_problem(96, 400.0, 0.1, storage=storage).with_(nx=80)
+    fields = W.rest_fields(80, 96, 1.0, 0.3)
+    a = Lattice(pr, device=DEV).init(*fields).set_graph(20)
+    e = Lattice(pr, device=DEV).init(*fields).set_graph(0)
+    for rep, n in enumerate((41, 40, 7, 60)):      # odd counts: eager start and remainder
+        a.step(n)
+        e.step(n)
+        torch.cuda.synchronize()
+        assert math.isfinite(torch.randn(1 << 16, device=DEV).sum().item())
+        fa, ga = a.get_populations(raw=True)
+        fb, gb = e.get_populations(raw=True)
+        assert torch.equal(fa, fb) and torch.equal(ga, gb), rep
+    assert a.step_count == e.step_count == 148
+
+
+@pytest.mark.parametrize("case", ["cavity_ragged", "fourroll"])
+def test_single_lattice_result_independent_of_tile_width(case):
+    say(f"case: tile widths {case}")
+    pr, fields = CASES[case]()
+    pr = pr.with_(storage="f32")
+    ref = None
+    for bx in (64, 128, 256, 512):
+        lat = Lattice(pr, device=DEV).init(*fields).set_tile_width(bx)
+        assert lat.tile_width == bx
+        lat.step(9)
+        pops = lat.get_populations(raw=True)
+        s = lat.reduce()
+        if ref is None:
+            ref = (pops, s)
+        else:
+            assert torch.equal(pops[0], ref[0][0]) and torch.equal(pops[1], ref[0][1]), bx
+            assert s["mass"] == ref[1]["mass"] and s["scalar"] == ref[1]["scalar"], bx
+
+
+def test_graph_capture_refused_where_the_step_depends_on_time():
+    pr = W.taylor_green_problem(16, storage="bf16sr")
+    lat = Lattice(pr, device=DEV).init(*W.taylor_green_fields(16, 0.01))
+    with pytest.raises(DDFError, match="UNSUPPORTED"):
+        lat.set_graph(20)
+    lat.set_graph(0).step(3)
