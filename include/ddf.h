@@ -50,7 +50,7 @@ typedef enum { DDF_F64 = 0, DDF_F32 = 1, DDF_F16 = 2, DDF_BF16 = 3, DDF_BF16_SR 
 typedef enum {
     DDF_OK = 0,
     DDF_ERR_ARG = -1,          /* invalid argument (message says which) */
-    DDF_ERR_UNSUPPORTED = -2,  /* valid request this build does not support */
+    DDF_ERR_UNSUPPORTED = -2,  /* valid request the library does not support */
     DDF_ERR_HIP = -3,          /* a HIP runtime call failed */
     DDF_ERR_NONFINITE = -4,    /* the state holds NaN or Inf */
     DDF_ERR_STATE = -5         /* call out of order (e.g. step before init) */

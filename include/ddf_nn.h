@@ -3,7 +3,7 @@
  *
  * The surrogate is a 2D U-Net that maps a lid-driven cavity's wall mask, Reynolds
  * number and lid speed to its steady fields (u, v, rho, phi); its prediction
- * warm-starts the lattice Boltzmann solver, which stays the judge of convergence.  It is
+ * warm-starts the lattice Boltzmann solver, which alone decides convergence.  It is
  * not part of the paper's method (arXiv:1908.06742); these entry points are the
  * building blocks its forward pass, backward pass and training step are made of.
  *

@@ -13,7 +13,7 @@ paper's D2Q9 order (Sec. 2, eq. particlevelocities1/2).
 Parity notes: every function here is pinned by ``tests/test_oracle_*.py``
 against closed forms, invariants and the matrices printed in App. B.  The
 scalar-model variants of App. C and App. D are pinned against each other and
-against the closed-form flows; see the design doc for the list.
+against the closed-form flows.
 """
 from __future__ import annotations
 

@@ -8,7 +8,7 @@ accumulation FP32 on the matrix cores, master weights and Adam state FP32.  Ever
 operation runs in the HIP kernels of include/ddf_nn.h; this module only allocates
 buffers (torch) and sequences the calls.
 
-The lattice Boltzmann solver stays the judge: a prediction only initialises the
+The lattice Boltzmann solver decides convergence: a prediction only initialises the
 lattice, and `warm_start_batch` falls back to a cold start for every instance whose
 residual after the first check (100 steps) is above 1e-2 or non-finite.
 """
@@ -326,7 +326,7 @@ def warm_start_batch(net, batch, re, u, cold_fields, check_steps=100, fallback_t
     steps and re-initialises at its cold state (cold_fields(i) -> (rho, ux, uy, phi))
     every instance whose velocity or scalar residual over those steps exceeds
     fallback_tol or that holds non-finite values.  Returns the fallback mask (numpy bool).
-    The lattice stays the judge: the prediction is only an initial state."""
+    The lattice Boltzmann run decides convergence: the prediction is only an initial state."""
     p0 = batch.problems[0]
     H, W = p0.ny, p0.nx
     if any(p.nx != W or p.ny != H for p in batch.problems):

@@ -85,7 +85,7 @@ def test_trained_network_shortens_the_run_to_steady_and_keeps_its_result():
     assert np.all(rc["status"] == "converged") and np.all(rw["status"] == "converged")
     assert s_warm.sum() * 2 <= s_cold.sum()
     assert s_warm.sum() * 2 <= s_untr.sum()
-    # the lattice is the judge: the warm-started steady state is the cold-started one
+    # the lattice decides convergence: the warm-started steady state is the cold-started one
     # (both stop at r < 1e-8, so they differ by about r over the slowest decay rate)
     for i in range(len(cases)):
         a = bc.extract(i, ["ux", "uy", "phi", "wz"])

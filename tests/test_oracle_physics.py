@@ -129,7 +129,7 @@ def test_poiseuille_vorticity(umax, model, nthreads):
     # Sec. 5.1: 3 x 151, F = 3e-6, walls half-way (L = 75.5), phi 1 and 2 on the walls,
     # tau_phi = 0.57.  Started from the parabola; omega is linear in y.  The rows next to
     # the Dirichlet scalar walls are excluded: anti-bounce-back flips the even part of the
-    # scalar's non-equilibrium there.
+    # scalar's non-equilibrium there, which the extraction reads as an O(1) error.
     ny, F = 151, 3e-6
     L = ny / 2.0
     nu = F * L * L / (2.0 * umax)
@@ -189,8 +189,9 @@ def test_fourroll_mill_re40(nthreads):
 
 def test_fourroll_second_order_convergence(nthreads):
     # Sec. 5.2.1 reports slope -2.0 of E_g,omega.  Refinement at fixed tau and Reynolds
-    # number (u0 ~ 1/N, diffusive scaling) gives it; the design doc explains why the literal
-    # acoustic scaling of the paper's parameters levels off near 1 %.
+    # number (u0 ~ 1/N, diffusive scaling) gives it; with the paper's parameters read
+    # literally (u0 fixed in lattice units, acoustic scaling) the error levels off near
+    # 1 % from the O(u^2) terms the Chapman-Enskog relations drop.
     tau = 0.8
     nu = (tau - 0.5) / 3.0
     errs = []
