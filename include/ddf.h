@@ -43,8 +43,9 @@ extern "C" {
  * F64 computes in double, the others in float.  F16 and BF16 round to nearest even.
  * BF16_SR stores bfloat16 with stochastic rounding: each stored population rounds up
  * with probability equal to the dropped fraction of an ulp, decided by a counter-based
- * hash of (slot, time step, lattice), so the stored values are unbiased and a run is
- * reproducible (also across a checkpoint resume at the same step). */
+ * hash of (slot, time step) whose two 16-bit halves serve the f and g lattices, so the
+ * stored values are unbiased and a run is reproducible (also across a checkpoint
+ * resume at the same step). */
 typedef enum { DDF_F64 = 0, DDF_F32 = 1, DDF_F16 = 2, DDF_BF16 = 3, DDF_BF16_SR = 4 } ddf_storage;
 
 typedef enum {

@@ -24,8 +24,8 @@ static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "diagona
 
 // ---------------------------------------------------------------------------
 // Storage codecs.  Stored value = encode(offset * scale); scale is a power of two.
-// enc takes a 32-bit key naming the population slot and time step; only the
-// stochastically rounded format uses it.
+// enc takes 16 uniform random bits (the low half of its argument); only the
+// stochastically rounded format uses them.
 // ---------------------------------------------------------------------------
 struct bf16 { uint16_t bits; };     // bfloat16, round to nearest even
 struct bf16sr { uint16_t bits; };   // bfloat16, stochastic rounding
@@ -42,16 +42,14 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x)
     return x;
 }
 
-// Key of one stored population: its slot index, the time step and the lattice (0 = f,
-// 1 = g).  Distinct (slot, step, lattice) give independent rounding decisions, and the
-// same ones give the same decisions (runs and checkpoint resumes are reproducible).
-__device__ __forceinline__ uint32_t sr_key(int64_t slot, uint32_t step_salt)
+// Uniform bits for the populations stored at one slot index at one time step: a hash
+// of (slot, step).  The f and g stores at that index take its low and high 16 bits, so
+// distinct (slot, step, lattice) get independent rounding decisions and the same ones
+// the same decisions (runs and checkpoint resumes are reproducible).
+__device__ __forceinline__ uint32_t sr_step_salt(int64_t t) { return mix32((uint32_t)t + 0x51ed27u); }
+__device__ __forceinline__ uint32_t sr_bits(int64_t slot, uint32_t step_salt)
 {
-    return ((uint32_t)slot * 0x9e3779b1u) ^ (uint32_t)(slot >> 32) ^ step_salt;
-}
-__device__ __forceinline__ uint32_t sr_step_salt(int64_t t, uint32_t lattice)
-{
-    return mix32((uint32_t)t * 2u + lattice + 0x51ed27u);
+    return mix32(((uint32_t)slot * 0x9e3779b1u) ^ (uint32_t)(slot >> 32) ^ step_salt);
 }
 
 template <class S> struct Codec;
@@ -92,7 +90,7 @@ template <> struct Codec<bf16> {
 template <> struct Codec<bf16sr> {
     using R = float;
     __device__ static float dec(bf16sr v) { return __uint_as_float(((uint32_t)v.bits) << 16); }
-    __device__ static bf16sr enc(float v, uint32_t key)
+    __device__ static bf16sr enc(float v, uint32_t bits)
     {
         uint32_t u = __float_as_uint(v);
         bf16sr r;
@@ -101,7 +99,7 @@ template <> struct Codec<bf16sr> {
         } else if ((u & 0x7f800000u) == 0x7f800000u) {  // infinities unchanged
             r.bits = (uint16_t)(u >> 16);
         } else {
-            u += mix32(key) & 0xffffu;
+            u += bits & 0xffffu;
             r.bits = (uint16_t)(u >> 16);
         }
         return r;

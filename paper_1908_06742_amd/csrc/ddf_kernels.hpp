@@ -145,10 +145,13 @@ __device__ __forceinline__ void step_node(S *__restrict__ f, S *__restrict__ g, 
     else collide_scalar_mrt(P, M, n, go);
 
     const int64_t cell = (int64_t)y * L.pitch + x;
-    const uint32_t kf = sr_step_salt(t, 0), kg = sr_step_salt(t, 1);
+    const uint32_t salt = sr_step_salt(t);
     // rest direction: same slot in both parities
-    f[cell] = Codec<S>::enc(fo[0] * P.scale, sr_key(cell, kf));
-    g[cell] = Codec<S>::enc(go[0] * P.scale, sr_key(cell, kg));
+    {
+        const uint32_t h = sr_bits(cell, salt);
+        f[cell] = Codec<S>::enc(fo[0] * P.scale, h);
+        g[cell] = Codec<S>::enc(go[0] * P.scale, h >> 16);
+    }
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
         int tx, ty;
@@ -166,8 +169,9 @@ __device__ __forceinline__ void step_node(S *__restrict__ f, S *__restrict__ g, 
         } else {
             slot = (int64_t)a * L.plane + (int64_t)ty * L.pitch + tx;
         }
-        f[slot] = Codec<S>::enc(vf * P.scale, sr_key(slot, kf));
-        g[slot] = Codec<S>::enc(vg * P.scale, sr_key(slot, kg));
+        const uint32_t h = sr_bits(slot, salt);
+        f[slot] = Codec<S>::enc(vf * P.scale, h);
+        g[slot] = Codec<S>::enc(vg * P.scale, h >> 16);
     }
 }
 
@@ -239,12 +243,13 @@ __global__ __launch_bounds__(kThreads) void k_init(S *__restrict__ f, S *__restr
     scalar_eq(P, M, n);
     populations(n, go);
     const int64_t cell = (int64_t)y * G.L.pitch + x;
-    const uint32_t kf = sr_step_salt(-1, 0), kg = sr_step_salt(-1, 1);
+    const uint32_t salt = sr_step_salt(-1);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         const int64_t s = (int64_t)a * G.L.plane + cell;
-        f[s] = Codec<S>::enc(fo[a] * P.scale, sr_key(s, kf));
-        g[s] = Codec<S>::enc(go[a] * P.scale, sr_key(s, kg));
+        const uint32_t h = sr_bits(s, salt);
+        f[s] = Codec<S>::enc(fo[a] * P.scale, h);
+        g[s] = Codec<S>::enc(go[a] * P.scale, h >> 16);
     }
 }
 
@@ -390,8 +395,9 @@ __global__ __launch_bounds__(kThreads) void k_set(S *__restrict__ f, S *__restri
         if (dtype == 0) {
             const double vf = ((const double *)fi)[a * N + c] - (double)P.rest_f[a] * (double)P.rho0;
             const double vg = ((const double *)gi)[a * N + c] - (double)P.rest_g[a] * (double)P.phi0;
-            f[s] = Codec<S>::enc((R)(vf * (double)P.scale), sr_key(s, sr_step_salt(-2, 0)));
-            g[s] = Codec<S>::enc((R)(vg * (double)P.scale), sr_key(s, sr_step_salt(-2, 1)));
+            const uint32_t h = sr_bits(s, sr_step_salt(-2));
+            f[s] = Codec<S>::enc((R)(vf * (double)P.scale), h);
+            g[s] = Codec<S>::enc((R)(vg * (double)P.scale), h >> 16);
         } else {
             f[s] = ((const S *)fi)[a * N + c];
             g[s] = ((const S *)gi)[a * N + c];
