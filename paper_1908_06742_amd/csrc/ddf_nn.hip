@@ -83,6 +83,86 @@ __global__ __launch_bounds__(64 * WM * WN) void k_conv3x3(const __bf16 *__restri
     }
 }
 
+// LDS-staged convolution (same contract as k_conv3x3).  A workgroup of four wavefronts
+// computes PB consecutive pixels of one image row against NCO tiles of 32 output
+// channels.  The reduction runs over (kernel row dy, 32-channel chunk): per stage the
+// input row y + dy with one pixel of halo on each side, and the weights of the row's
+// three taps, are staged into LDS with 16-byte loads; then each wavefront applies the
+// three taps (a dx shift moves whole pixels, so the 16-byte operand reads stay aligned)
+// to its TPW output tiles.  Staged inputs feed 3 NCO MFMA tiles, staged weights PB / 32.
+template <int PB, int NCO>
+__global__ __launch_bounds__(256) void k_conv3x3_lds(const __bf16 *__restrict__ in, int N, int H, int W, int Cin,
+                                                     int in_cs, int in_co, const __bf16 *__restrict__ wt,
+                                                     const float *__restrict__ bias, __bf16 *__restrict__ out,
+                                                     int Cout, int out_cs, int out_co, int relu, int accumulate)
+{
+    constexpr int PMT = PB / 32;                 // pixel tiles
+    constexpr int TPW = PMT * NCO / 4;           // output tiles per wavefront
+    static_assert(TPW >= 1 && PMT * NCO == 4 * TPW, "four wavefronts share the tiles evenly");
+    constexpr int RS = 40;                       // LDS row stride (32 channels + 8 of padding)
+    __shared__ __attribute__((aligned(16))) __bf16 xs[PB + 2][RS];
+    __shared__ __attribute__((aligned(16))) __bf16 ws[3][32 * NCO][RS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = lane & 31, half = lane >> 5;
+    const int segs = W / PB;
+    const int64_t row = blockIdx.x / segs;       // n * H + y
+    const int x0 = (int)(blockIdx.x % segs) * PB;
+    const int y = (int)(row % H);
+    const int co0 = blockIdx.y * 32 * NCO;
+    f32x16 acc[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[t][j] = 0.0f;
+    for (int dy = 0; dy < 3; ++dy) {
+        const int yy = y + dy - 1;
+        const bool row_ok = yy >= 0 && yy < H;
+        for (int c0 = 0; c0 < Cin; c0 += 32) {
+            for (int v = tid; v < (PB + 2) * 4; v += 256) {
+                const int c8 = v & 3, px = v >> 2, xx = x0 + px - 1;
+                bf16x8 val = zero8();
+                if (row_ok && xx >= 0 && xx < W)
+                    val = load8(in + ((row + dy - 1) * W + xx) * in_cs + in_co + c0 + 8 * c8);
+                *(bf16x8 *)&xs[px][8 * c8] = val;
+            }
+            for (int v = tid; v < 3 * 32 * NCO * 4; v += 256) {
+                const int c8 = v & 3, q = v >> 2, co = q % (32 * NCO), dx = q / (32 * NCO);
+                *(bf16x8 *)&ws[dx][co][8 * c8] =
+                    load8(wt + ((int64_t)(3 * dy + dx) * Cout + co0 + co) * Cin + c0 + 8 * c8);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+#pragma unroll
+                    for (int t = 0; t < TPW; ++t) {
+                        const int tile = wave * TPW + t, pm = tile % PMT, cn = tile / PMT;
+                        const bf16x8 a = *(const bf16x8 *)&xs[32 * pm + m + dx][16 * k + 8 * half];
+                        const bf16x8 b = *(const bf16x8 *)&ws[dx][32 * cn + m][16 * k + 8 * half];
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+                    }
+                }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int tile = wave * TPW + t, pm = tile % PMT, cn = tile / PMT;
+        const int co = co0 + 32 * cn + m;
+        const float bv = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int64_t pr = row * W + x0 + 32 * pm + 8 * (j >> 2) + 4 * half + (j & 3);
+            __bf16 *o = out + pr * out_cs + out_co + co;
+            float v = acc[t][j] + bv;
+            if (relu) v = fmaxf(v, 0.0f);
+            if (accumulate) v += (float)*o;
+            *o = (__bf16)v;
+        }
+    }
+}
+
 // Split-K weight gradient: part[chunk][tap][co][ci] = sum over the chunk's pixels p of
 // dout[p, co] * in[p + d(tap), ci].  One wavefront per (ci tile, co tile, tap, chunk).
 __global__ __launch_bounds__(64) void k_conv3x3_wgrad(const __bf16 *__restrict__ in, int N, int H, int W, int Cin,
@@ -630,7 +710,15 @@ int ddf_nn_conv3x3(const void *in, int32_t N, int32_t H, int32_t W, int32_t Cin,
     const __bf16 *i = (const __bf16 *)in;
     const __bf16 *w = (const __bf16 *)wt;
     __bf16 *o = (__bf16 *)out;
-    if (Cout % 64 == 0 && npix % 64 == 0)
+    const bool lds = Cin % 32 == 0 && al16(in) && al16(wt);
+#define DDF_CONV_LDS(PB, NCO)                                                                                      \
+    hipLaunchKernelGGL((k_conv3x3_lds<PB, NCO>), dim3((unsigned)(npix / PB), (unsigned)(Cout / (32 * NCO))), dim3(256), \
+                       0, st, i, N, H, W, Cin, in_cs, in_co, w, bias, o, Cout, out_cs, out_co, relu, accumulate)
+    if (lds && W % 64 == 0 && Cout % 128 == 0) DDF_CONV_LDS(64, 4);
+    else if (lds && W % 64 == 0 && Cout % 64 == 0) DDF_CONV_LDS(64, 2);
+    else if (lds && W % 32 == 0 && Cout % 128 == 0) DDF_CONV_LDS(32, 4);
+    else if (lds && W % 128 == 0) DDF_CONV_LDS(128, 1);
+    else if (Cout % 64 == 0 && npix % 64 == 0)
         hipLaunchKernelGGL((k_conv3x3<2, 2>), dim3(npix / 64, Cout / 64), dim3(256), 0, st, i, N, H, W, Cin, in_cs,
                            in_co, w, bias, o, Cout, out_cs, out_co, relu, accumulate);
     else if (npix % 128 == 0)
@@ -639,6 +727,7 @@ int ddf_nn_conv3x3(const void *in, int32_t N, int32_t H, int32_t W, int32_t Cin,
     else
         hipLaunchKernelGGL((k_conv3x3<1, 1>), dim3(npix / 32, Cout / 32), dim3(64), 0, st, i, N, H, W, Cin, in_cs,
                            in_co, w, bias, o, Cout, out_cs, out_co, relu, accumulate);
+#undef DDF_CONV_LDS
     return check_launch();
 }
 

@@ -326,3 +326,28 @@ def test_elementwise_kernels_with_unaligned_channel_counts():
     got = np_of(gg, x.shape).reshape(-1)
     ref = np.where(x > 0, x, 0.0).reshape(-1)
     assert np.array_equal(got[:-3], ref[:-3]) and np.array_equal(got[-3:], x.reshape(-1)[-3:])
+
+
+@pytest.mark.parametrize("B,H,W,Cin,Cout,cs_in,co_in,cs_out,co_out,acc", [
+    (1, 3, 64, 64, 128, 64, 0, 128, 0, 0),       # 64-pixel segments, 4 channel tiles
+    (2, 2, 128, 32, 64, 64, 16, 96, 32, 1),      # 64-pixel segments, 2 tiles, slices, accumulate
+    (1, 4, 32, 96, 128, 96, 0, 128, 0, 0),       # 32-pixel segments, 4 tiles
+    (1, 3, 256, 64, 32, 64, 0, 64, 32, 1),       # 128-pixel segments, 1 tile
+])
+def test_conv3x3_lds_configs(B, H, W, Cin, Cout, cs_in, co_in, cs_out, co_out, acc):
+    r = np.random.default_rng(B + H + W + Cin + Cout)
+    xt, x = bf(r.standard_normal((B, H, W, cs_in)))
+    wt, wq = bf(r.standard_normal((9, Cout, Cin)) / np.sqrt(9 * Cin))
+    b = r.standard_normal(Cout).astype(np.float32)
+    bt = torch.tensor(b, device=DEV)
+    out0, out0q = bf(r.standard_normal((B, H, W, cs_out)))
+    L.check(L.lib().ddf_nn_conv3x3(p(xt), B, H, W, Cin, cs_in, co_in, p(wt), p(bt), p(out0), Cout, cs_out, co_out, 1,
+                                   acc, s0()))
+    ref = np.maximum(U.conv3x3(x[..., co_in:co_in + Cin], wq.reshape(9, Cout, Cin), b.astype(np.float64)), 0)
+    if acc:
+        ref = ref + out0q[..., co_out:co_out + Cout]
+    got = np_of(out0, (B, H, W, cs_out))
+    assert rel(got[..., co_out:co_out + Cout], ref) < 1e-2
+    untouched = np.ones(cs_out, bool)
+    untouched[co_out:co_out + Cout] = False
+    assert np.array_equal(got[..., untouched], out0q[..., untouched])
