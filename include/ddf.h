@@ -213,14 +213,16 @@ int ddf_batch_offsets(const ddf_batch *b, int32_t i, int64_t *pop_offset_bytes, 
  * (same rule as ddf_init_equilibrium); resets the step counter. */
 int ddf_batch_init_equilibrium(ddf_batch *b, const double *rho, const double *ux, const double *uy,
                                const double *phi, void *stream);
-/* Tiling: tile width at most bx_max (64, 128, 256 or 512; kThreads = 512 threads per
- * tile) and blocks_per_cu persistent workgroups per compute unit (0 = one workgroup per
- * tile).  Invalidates the captured graph. */
+/* Tiling: tile width at most bx_max (64, 128, 256 or 512; 512 threads per tile), or
+ * bx_max = 0 for flat tiles of 512 consecutive nodes in row-major order (instances whose
+ * sides are not multiples of a tile then leave idle lanes only in their last tile); and
+ * blocks_per_cu persistent workgroups per compute unit (0 = one workgroup per tile).
+ * Results do not depend on the tiling.  Invalidates the captured graph. */
 int ddf_batch_set_tiling(ddf_batch *b, int32_t bx_max, int32_t blocks_per_cu);
 int ddf_batch_get_tiling(const ddf_batch *b, int32_t *bx_max, int32_t *blocks_per_cu, int32_t *ntiles, int32_t *grid);
-/* Times every (bx_max, blocks_per_cu) candidate for steps_per_trial steps on this
- * instance mix, applies the fastest and caches it per (storage, instance sizes) for the
- * process.  The trials overwrite the populations: call it before
+/* Times every (bx_max, blocks_per_cu) candidate (bx_max 0, 64, 128, 256 or 512) for
+ * steps_per_trial steps on this instance mix, applies the fastest and caches it per
+ * (storage, instance sizes) for the process.  The trials overwrite the populations: call it before
  * ddf_batch_init_equilibrium.  best_ms_per_step is -1 when the cache answered. */
 int ddf_batch_autotune(ddf_batch *b, int32_t steps_per_trial, int32_t *bx_max, int32_t *blocks_per_cu,
                        float *best_ms_per_step, void *stream);

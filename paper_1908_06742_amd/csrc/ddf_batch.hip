@@ -30,9 +30,29 @@ struct InstDesc {
     Lat L;
     int64_t off;        // element offset of this instance's planes in f and g
     int64_t snap_off;   // element offset of its residual snapshot (3 * nx * ny)
-    int bx_shift, by, tiles_x, ntiles;
+    int bx_shift, by, tiles_x, ntiles;   // bx_shift < 0: flat tiles (see inst_node)
     Phys<R> P;
 };
+
+// Node of this thread in tile `tile` of an instance.  Rectangular tiles are
+// 2^bx_shift x by nodes; flat tiles are kThreads consecutive nodes in row-major order,
+// so an instance whose sides are not multiples of the tile leaves idle lanes only in
+// its last tile.
+template <class R>
+__device__ __forceinline__ bool inst_node(const InstDesc<R> &D, int tile, int &x, int &y)
+{
+    if (D.bx_shift < 0) {
+        // nx * ny <= 2^31, so the node index fits 32-bit unsigned arithmetic
+        const uint32_t idx = (uint32_t)tile * kThreads + threadIdx.x;
+        const uint32_t nx = (uint32_t)D.L.nx;
+        if (idx >= nx * (uint32_t)D.L.ny) return false;
+        const uint32_t yy = idx / nx;
+        y = (int)yy;
+        x = (int)(idx - yy * nx);
+        return true;
+    }
+    return tile_node(tile, D.bx_shift, D.by, D.tiles_x, D.L.nx, D.L.ny, x, y);
+}
 
 struct TileRef {
     int inst;
@@ -52,7 +72,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(S *__restrict__ f, S *_
         const TileRef tr = tiles[k];
         const auto &D = inst[tr.inst];
         int x, y;
-        if (tile_node(tr.tile, D.bx_shift, D.by, D.tiles_x, D.L.nx, D.L.ny, x, y))
+        if (inst_node(D, tr.tile, x, y))
             step_node<S, SCALAR, true, true, ODD>(f + D.off, g + D.off, D.L, D.P, x, y, t);
     }
 }
@@ -71,7 +91,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_reduce(const S *__restrict__
     double v[RS_N];
     stats_identity(v);
     int x, y;
-    if (tile_node(tr.tile, D.bx_shift, D.by, D.tiles_x, D.L.nx, D.L.ny, x, y))
+    if (inst_node(D, tr.tile, x, y))
         node_stats<S, true, ODD>(f + D.off, g + D.off, D.L, D.P, x, y, t, snap + D.snap_off, snap_valid, v);
     block_reduce_stats<kThreads>(sh, v, partials + (int64_t)blockIdx.x * RS_N);
 }
@@ -94,7 +114,7 @@ std::mutex &tune_mutex()
     return m;
 }
 
-const int kBxCandidates[] = {64, 128, 256, 512};
+const int kBxCandidates[] = {0, 64, 128, 256, 512};   // 0: flat tiles
 const int kBpcCandidates[] = {0, 2, 4, 8};   // 0: one workgroup per tile
 
 }  // namespace
@@ -139,6 +159,7 @@ size_t inst_desc_size(int storage) { return storage == DDF_F64 ? sizeof(InstDesc
 
 int tiles_of(const ddf_params &p, int bx_max)
 {
+    if (bx_max == 0) return (int)(((int64_t)p.nx * p.ny + kThreads - 1) / kThreads);
     const Geom G = make_geom(p, bx_max);
     return G.ntiles;
 }
@@ -193,19 +214,19 @@ void fill_desc(const ddf_batch *b, std::vector<InstDesc<R>> &d, std::vector<Tile
     d.resize(b->n);
     tl.clear();
     for (int i = 0; i < b->n; ++i) {
-        const Geom G = make_geom(b->p[i], b->bx_max);
+        const Geom G = make_geom(b->p[i], b->bx_max == 0 ? kThreads : b->bx_max);
         InstDesc<R> &D = d[i];
         std::memset(&D, 0, sizeof(D));
         D.L = G.L;
         D.off = b->off[i];
         D.snap_off = 3 * b->node_off[i];
-        D.bx_shift = G.bx_shift;
+        D.bx_shift = b->bx_max == 0 ? -1 : G.bx_shift;
         D.by = G.by;
         D.tiles_x = G.tiles_x;
-        D.ntiles = G.ntiles;
+        D.ntiles = tiles_of(b->p[i], b->bx_max);
         if constexpr (std::is_same<R, double>::value) D.P = b->P[i].d;
         else D.P = b->P[i].f;
-        for (int k = 0; k < G.ntiles; ++k) tl.push_back(TileRef{i, k});
+        for (int k = 0; k < D.ntiles; ++k) tl.push_back(TileRef{i, k});
     }
 }
 
@@ -489,7 +510,7 @@ int ddf_batch_set_tiling(ddf_batch *b, int32_t bx_max, int32_t blocks_per_cu)
     if (!b) return fail(DDF_ERR_ARG, "batch is NULL");
     bool ok = false;
     for (int c : kBxCandidates) ok |= (c == bx_max);
-    if (!ok) return fail(DDF_ERR_ARG, "bx_max must be 64, 128, 256 or 512");
+    if (!ok) return fail(DDF_ERR_ARG, "bx_max must be 0 (flat tiles), 64, 128, 256 or 512");
     if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(DDF_ERR_ARG, "blocks_per_cu must lie in [0, 64]");
     int rc = quiesce();
     if (rc != DDF_OK) return rc;

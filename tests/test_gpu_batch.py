@@ -99,7 +99,7 @@ def test_result_independent_of_tiling():
     say("case: batch tilings")
     items = mixed_problems("f32")
     ref = None
-    for bx in (64, 128, 256, 512):
+    for bx in (0, 64, 128, 256, 512):     # 0: flat tiles
         for bpc in (0, 2, 8):
             b = Batch([p for p, _ in items], device=DEV)
             b.set_tiling(bx, bpc)
@@ -117,7 +117,7 @@ def test_autotune_then_run():
     items = mixed_problems("f32")
     b = Batch([p for p, _ in items], device=DEV)
     t = b.autotune(steps_per_trial=4)
-    assert t["bx_max"] in (64, 128, 256, 512) and t["blocks_per_cu"] in (0, 2, 4, 8) and t["ms_per_step"] > 0
+    assert t["bx_max"] in (0, 64, 128, 256, 512) and t["blocks_per_cu"] in (0, 2, 4, 8) and t["ms_per_step"] > 0
     b.init([f for _, f in items]).step(10)
     s = b.reduce()
     assert np.all(s["nonfinite"] == 0)
