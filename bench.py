@@ -48,7 +48,8 @@ def measured_traffic(nodes, tile_width):
     return d.get("bytes_per_launch")
 
 
-def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=None):
+def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=None, scalar_model="mrt",
+            pulsatile=False, time_extract=False):
     import numpy as np
     import torch
 
@@ -56,7 +57,10 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=No
     from paper_1908_06742_amd import Lattice
 
     vf = W.VortexField(L=L) if L == 8192 else W.VortexField(L=L, sigma=32.0 * L / 8192, n_blobs=max(16, 1024 * L * L // (8192 * 8192)))
-    pr = W.vortex_problem(L, storage=storage)
+    pr = W.vortex_problem(L, storage=storage, scalar_model=scalar_model)
+    if pulsatile:
+        # time-periodic uniform body force (the Womersley forcing), small against the field
+        pr = pr.with_(force_kind="pulsatile", force=(1e-6, 0.0), force_omega=2.0 * np.pi / 1000.0)
     fields = vf.eval_grid(np.arange(L), np.arange(L), device="cuda")
     lat = Lattice(pr, device="cuda").init(*fields)
     if tile_width:
@@ -93,6 +97,16 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=No
     dt = time.perf_counter() - t0
     kern_ms = sum(a.elapsed_time(b) for a, b in evs) / (steps * lb_steps)
     stats = dict(last)
+    extract_ms = None
+    if time_extract:
+        # all 16 outputs (rho, u, phi, S, omega, gradients, Q, R, Lamb vector) in FP32
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            lat.extract(out=out)
+        e1.record(stream)
+        e1.synchronize()
+        extract_ms = e0.elapsed_time(e1) / 5
     nodes = L * L
     return {
         "nodes": nodes,
@@ -102,6 +116,7 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=No
         "kernel_ms": kern_ms,
         "stats": stats,
         "tile_width": tile_width,
+        "extract_ms": extract_ms,
     }
 
 
@@ -457,12 +472,25 @@ def main():
         line["extras"]["unet256_train_b8"] = run_unet()
     if args.variants:
         var = []
-        for st, L in (("f16", 8192), ("bf16", 8192), ("bf16sr", 8192), ("f64", 8192)):
-            print(f"[bench] variant {L}^2 {st}", file=sys.stderr, flush=True)
-            v = run_gpu(L, st, 3, 1)
+        cases = [dict(storage="f16"), dict(storage="bf16"), dict(storage="bf16sr"), dict(storage="f64"),
+                 dict(storage="f32", scalar_model="srt"), dict(storage="f32", scalar_model="central"),
+                 dict(storage="f32", scalar_model="cascaded"), dict(storage="f32", pulsatile=True),
+                 dict(storage="f32", time_extract=True)]
+        for c in cases:
+            st = c["storage"]
+            print(f"[bench] variant 8192^2 {c}", file=sys.stderr, flush=True)
+            v = run_gpu(8192, st, 3, 1, scalar_model=c.get("scalar_model", "mrt"), pulsatile=c.get("pulsatile", False),
+                        time_extract=c.get("time_extract", False))
             ach = BYTES_PER_NODE[st] * v["nodes"] / (v["kernel_ms"] * 1e-3) / 1e9
-            var.append({"storage": st, "size": L, "mlups": round(v["mlups"], 1),
-                        "kernel_gbs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4)})
+            row = {**c, "size": 8192, "mlups": round(v["mlups"], 1), "kernel_gbs": round(ach, 1),
+                   "frac": round(ach / HBM_PEAK_GBS, 4), "tile_width": v["tile_width"]}
+            if v["extract_ms"] is not None:
+                # reads both lattices once (half the step's bytes: 72 B/node in FP32) and
+                # writes 16 FP32 outputs (64 B/node)
+                eb = (BYTES_PER_NODE[st] // 2 + 64) * v["nodes"] / (v["extract_ms"] * 1e-3) / 1e9
+                row.update({"extract_all_ms": round(v["extract_ms"], 3), "extract_gbs": round(eb, 1),
+                            "extract_frac": round(eb / HBM_PEAK_GBS, 4)})
+            var.append(row)
         line["variants"] = var
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
