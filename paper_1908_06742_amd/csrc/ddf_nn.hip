@@ -205,15 +205,35 @@ __global__ __launch_bounds__(64) void k_conv3x3_wgrad(const __bf16 *__restrict__
     }
 }
 
+// MFMA operand of 8 consecutive pixels at one channel from a [pixel][channel] LDS tile,
+// by two gfx950 transpose reads (ds_read_b64_tr_b16).  Within each 16-lane group, output
+// lane t receives, in slot s, element t mod 4 of the 8-byte chunk addressed by group lane
+// 4 s + t / 4.  So group lane i points at (pixel row + i / 4, channel + 4 (i mod 4)), and
+// lane t gets 4 consecutive pixels of channel + t.  The caller passes the lane's address
+// p = &tile[k0 + 8 (lane / 32) + (lane mod 16) / 4][32 tile + 16 ((lane / 16) mod 2) +
+// 4 (lane mod 4)]; the second read starts 4 rows further.  The result is the MFMA layout:
+// lane l holds rows m = l mod 32, k = 8 (l / 32) .. + 7.  The two halves are joined and
+// reinterpreted as whole vectors: converting them element by element (bit-casting each
+// short to __bf16) compiles, with this toolchain at -O3, to code that keeps only the first
+// short of every pair.
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ bf16x8 tr_operand(const __bf16 *p, int row_stride)
+{
+    typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
+    const i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)p);
+    const i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(p + 4 * row_stride));
+    return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
 // LDS-staged weight gradient.  A workgroup of three wavefronts, one per kernel row
 // (dy = -1, 0, 1), walks a run of pixel blocks; a block is PB consecutive pixels of one
 // image row.  Per block it stages with 16-byte loads the output gradient dout[PB][32 CO_T]
 // and the three input rows in[y-1 .. y+1][x0-1 .. x0+PB] (zero outside the image); then
 // each wavefront contracts over the block's pixels for its three taps (dx = -1, 0, 1)
 // and its CO_T x CI_T output tiles of 32 x 32, so each staged value feeds several MFMAs.
-// The contraction runs over pixels, which NHWC keeps strided, so operands are gathered
-// from LDS as 8 single bf16 values per lane; rows are padded by 8 elements so that the
-// two half-waves (pixel offsets 0 and 8) read disjoint banks.
+// The contraction runs over pixels, which NHWC keeps strided: operands come out of the
+// [pixel][channel] tiles by transpose reads (tr_operand); rows are padded by 8 elements.
 // part[chunk][tap][co][ci] receives the chunk's sums (tap = 3 (dy + 1) + dx + 1).  The
 // workgroups of the first input-channel tile also sum the staged output gradient over
 // the chunk's pixels into bpart[chunk][co] (bias gradient), in a fixed order.
@@ -233,6 +253,9 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(const __bf16 *__restrict__ in
     const int tiles_ci = Cin / (32 * CI_T);
     const int ci0 = (blockIdx.x % tiles_ci) * 32 * CI_T, co0 = (blockIdx.x / tiles_ci) * 32 * CO_T;
     const bool bias = bpart != nullptr && blockIdx.x % tiles_ci == 0;
+    // transpose-read geometry (see tr_operand): pixel row and channel offsets of this lane
+    const int tr_row = 8 * (lane >> 5) + ((lane & 15) >> 2);
+    const int tr_col = 16 * ((lane >> 4) & 1) + 4 * (lane & 3);
     float bsum[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) bsum[i] = 0.0f;
@@ -278,19 +301,14 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(const __bf16 *__restrict__ in
         __syncthreads();
 #pragma unroll
         for (int k0 = 0; k0 < PB; k0 += 16) {
-            const int kk = k0 + 8 * half;
             bf16x8 a[CO_T];
 #pragma unroll
-            for (int t = 0; t < CO_T; ++t)
-#pragma unroll
-                for (int i = 0; i < 8; ++i) a[t][i] = ds[kk + i][32 * t + m];
+            for (int t = 0; t < CO_T; ++t) a[t] = tr_operand(&ds[k0 + tr_row][32 * t + tr_col], DS);
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
 #pragma unroll
                 for (int u = 0; u < CI_T; ++u) {
-                    bf16x8 b;
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) b[i] = xs[r][kk + i + dx][32 * u + m];
+                    const bf16x8 b = tr_operand(&xs[r][k0 + tr_row + dx][32 * u + tr_col], XS);
 #pragma unroll
                     for (int t = 0; t < CO_T; ++t)
                         acc[dx][t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[t], b, acc[dx][t][u], 0, 0, 0);
