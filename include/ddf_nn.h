@@ -41,8 +41,9 @@ size_t ddf_nn_wgrad_workspace_bytes(int32_t N, int32_t H, int32_t W, int32_t Cin
 /* dw[tap][co][ci] (= or +=) sum_p dout[p, co] in[p + d(tap), in_co + ci] in FP32, with
  * split-K partials summed in a fixed order (deterministic); db[co] (= or +=)
  * sum_p dout[p, co] if db is not NULL.  Requires Cin % 32 == 0, Cout % 32 == 0,
- * Cout <= 256, channel strides and offsets multiples of 8 and 16-byte aligned tensors.
- * Rows of W % 16 == 0 pixels take the LDS-staged kernel, others a gather kernel. */
+ * Cout <= 256, channel strides and offsets multiples of 8, and 16-byte aligned tensors
+ * and workspace (else DDF_ERR_ARG).  Rows of W % 16 == 0 pixels take the LDS-staged
+ * kernel, others a gather kernel. */
 int ddf_nn_conv3x3_wgrad(const void *in, int32_t N, int32_t H, int32_t W, int32_t Cin, int32_t in_cs, int32_t in_co,
                          const void *dout, int32_t Cout, int32_t d_cs, float *dw, float *db, int32_t accumulate,
                          void *workspace, void *stream);

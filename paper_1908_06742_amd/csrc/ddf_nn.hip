@@ -114,37 +114,62 @@ __global__ __launch_bounds__(256) void k_conv3x3_lds(const __bf16 *__restrict__ 
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
         for (int j = 0; j < 16; ++j) acc[t][j] = 0.0f;
-    for (int dy = 0; dy < 3; ++dy) {
+    // Stages (kernel row dy, 32-channel chunk c0) in dy-major order.  Staging is
+    // software-pipelined: the global loads of stage s + 1 are issued into registers before
+    // the MFMAs of stage s and written to LDS after them.
+    constexpr int XV = (PB + 2) * 4;             // 16-byte input vectors per stage
+    constexpr int WV = 3 * 32 * NCO * 4;         // 16-byte weight vectors per stage
+    constexpr int NXV = (XV + 255) / 256, NWV = (WV + 255) / 256;
+    bf16x8 xr[NXV], wr[NWV];
+    const int nc = Cin / 32, nst = 3 * nc;
+    auto fetch = [&](int s) {
+        const int dy = s / nc, c0 = 32 * (s - dy * nc);
         const int yy = y + dy - 1;
         const bool row_ok = yy >= 0 && yy < H;
-        for (int c0 = 0; c0 < Cin; c0 += 32) {
-            for (int v = tid; v < (PB + 2) * 4; v += 256) {
-                const int c8 = v & 3, px = v >> 2, xx = x0 + px - 1;
-                bf16x8 val = zero8();
-                if (row_ok && xx >= 0 && xx < W)
-                    val = load8(in + ((row + dy - 1) * W + xx) * in_cs + in_co + c0 + 8 * c8);
-                *(bf16x8 *)&xs[px][8 * c8] = val;
-            }
-            for (int v = tid; v < 3 * 32 * NCO * 4; v += 256) {
-                const int c8 = v & 3, q = v >> 2, co = q % (32 * NCO), dx = q / (32 * NCO);
-                *(bf16x8 *)&ws[dx][co][8 * c8] =
-                    load8(wt + ((int64_t)(3 * dy + dx) * Cout + co0 + co) * Cin + c0 + 8 * c8);
-            }
-            __syncthreads();
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx)
-#pragma unroll
-                for (int k = 0; k < 2; ++k) {
-#pragma unroll
-                    for (int t = 0; t < TPW; ++t) {
-                        const int tile = wave * TPW + t, pm = tile % PMT, cn = tile / PMT;
-                        const bf16x8 a = *(const bf16x8 *)&xs[32 * pm + m + dx][16 * k + 8 * half];
-                        const bf16x8 b = *(const bf16x8 *)&ws[dx][32 * cn + m][16 * k + 8 * half];
-                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
-                    }
-                }
-            __syncthreads();
+        for (int i = 0; i < NXV; ++i) {
+            const int v = tid + 256 * i;
+            const int c8 = v & 3, px = v >> 2, xx = x0 + px - 1;
+            xr[i] = zero8();
+            if (v < XV && row_ok && xx >= 0 && xx < W)
+                xr[i] = load8(in + ((row + dy - 1) * W + xx) * in_cs + in_co + c0 + 8 * c8);
         }
+#pragma unroll
+        for (int i = 0; i < NWV; ++i) {
+            const int v = tid + 256 * i;
+            const int c8 = v & 3, q = v >> 2, co = q % (32 * NCO), dx = q / (32 * NCO);
+            wr[i] = zero8();
+            if (v < WV) wr[i] = load8(wt + ((int64_t)(3 * dy + dx) * Cout + co0 + co) * Cin + c0 + 8 * c8);
+        }
+    };
+    fetch(0);
+    for (int s = 0; s < nst; ++s) {
+#pragma unroll
+        for (int i = 0; i < NXV; ++i) {
+            const int v = tid + 256 * i;
+            if (v < XV) *(bf16x8 *)&xs[v >> 2][8 * (v & 3)] = xr[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NWV; ++i) {
+            const int v = tid + 256 * i;
+            const int q = v >> 2;
+            if (v < WV) *(bf16x8 *)&ws[q / (32 * NCO)][q % (32 * NCO)][8 * (v & 3)] = wr[i];
+        }
+        __syncthreads();
+        if (s + 1 < nst) fetch(s + 1);
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+#pragma unroll
+                for (int t = 0; t < TPW; ++t) {
+                    const int tile = wave * TPW + t, pm = tile % PMT, cn = tile / PMT;
+                    const bf16x8 a = *(const bf16x8 *)&xs[32 * pm + m + dx][16 * k + 8 * half];
+                    const bf16x8 b = *(const bf16x8 *)&ws[dx][32 * cn + m][16 * k + 8 * half];
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+                }
+            }
+        __syncthreads();
     }
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
@@ -273,32 +298,57 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(const __bf16 *__restrict__ in
             for (int b = 0; b < CI_T; ++b)
 #pragma unroll
                 for (int j = 0; j < 16; ++j) acc[dx][a][b][j] = 0.0f;
-    for (int64_t blk = b0; blk < b1; ++blk) {
+    // Staging is software-pipelined: the global loads of block blk + 1 are issued into
+    // registers before the MFMAs of block blk and written to LDS after them.
+    constexpr int XV = 3 * (PB + 2) * 4 * CI_T;   // 16-byte input vectors per block
+    constexpr int DV = PB * 4 * CO_T;             // 16-byte output-gradient vectors per block
+    constexpr int NXV = (XV + 191) / 192, NDV = (DV + 191) / 192;
+    bf16x8 xr[NXV], dr[NDV];
+    auto fetch = [&](int64_t blk) {
         const int x0 = (int)(blk % bpr) * PB;
         const int64_t row = blk / bpr;   // n * H + y
         const int y = (int)(row % H);
-        constexpr int XV = 3 * (PB + 2) * 4 * CI_T;
-        for (int v = tid; v < XV; v += 192) {
+#pragma unroll
+        for (int i = 0; i < NXV; ++i) {
+            const int v = tid + 192 * i;
             const int c8 = v % (4 * CI_T), q = v / (4 * CI_T);
             const int px = q % (PB + 2), rr = q / (PB + 2);
             const int yy = y + rr - 1, xx = x0 + px - 1;
-            bf16x8 val = zero8();
-            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                val = load8(in + ((row + rr - 1) * W + xx) * in_cs + in_co + ci0 + 8 * c8);
-            *(bf16x8 *)&xs[rr][px][8 * c8] = val;
+            xr[i] = zero8();
+            if (v < XV && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                xr[i] = load8(in + ((row + rr - 1) * W + xx) * in_cs + in_co + ci0 + 8 * c8);
         }
-        constexpr int DV = PB * 4 * CO_T;
-        // 192 is a multiple of 4 CO_T: a thread keeps one group of 8 channels
-        for (int v = tid; v < DV; v += 192) {
-            const int c8 = v % (4 * CO_T), px = v / (4 * CO_T);
-            const bf16x8 dv = load8(dout + (row * W + x0 + px) * d_cs + co0 + 8 * c8);
-            *(bf16x8 *)&ds[px][8 * c8] = dv;
-            if (bias) {
 #pragma unroll
-                for (int i = 0; i < 8; ++i) bsum[i] += (float)dv[i];
+        for (int i = 0; i < NDV; ++i) {
+            const int v = tid + 192 * i;
+            const int c8 = v % (4 * CO_T), px = v / (4 * CO_T);
+            dr[i] = zero8();
+            if (v < DV) dr[i] = load8(dout + (row * W + x0 + px) * d_cs + co0 + 8 * c8);
+        }
+    };
+    if (b0 < b1) fetch(b0);
+    for (int64_t blk = b0; blk < b1; ++blk) {
+#pragma unroll
+        for (int i = 0; i < NXV; ++i) {
+            const int v = tid + 192 * i;
+            const int c8 = v % (4 * CI_T), q = v / (4 * CI_T);
+            if (v < XV) *(bf16x8 *)&xs[q / (PB + 2)][q % (PB + 2)][8 * c8] = xr[i];
+        }
+        // 192 is a multiple of 4 CO_T: a thread keeps one group of 8 channels
+#pragma unroll
+        for (int i = 0; i < NDV; ++i) {
+            const int v = tid + 192 * i;
+            const int c8 = v % (4 * CO_T), px = v / (4 * CO_T);
+            if (v < DV) {
+                *(bf16x8 *)&ds[px][8 * c8] = dr[i];
+                if (bias) {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) bsum[j] += (float)dr[i][j];
+                }
             }
         }
         __syncthreads();
+        if (blk + 1 < b1) fetch(blk + 1);
 #pragma unroll
         for (int k0 = 0; k0 < PB; k0 += 16) {
             bf16x8 a[CO_T];
@@ -343,26 +393,41 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(const __bf16 *__restrict__ in
     }
 }
 
-// out[i] (= or +=) sum_c part[c][i] over c = 0 .. nchunk-1, in a fixed order: in a block
-// of 32 elements x 8 chunk groups, thread (e, q) sums the chunks c = q, q + 8, ... of
-// element e in increasing c, then the eight group sums are added for q = 0 .. 7.
+// out[i] (= or +=) sum_c part[c][i] over c = 0 .. nchunk-1, in a fixed order: a block of
+// 256 threads covers 4 (256 / G) elements, as 256 / G groups of 4 consecutive elements
+// (one 16-byte load) x G chunk groups; thread (e4, q) sums the chunks c = q, q + G, ...
+// of its 4 elements in increasing c, then the G group sums of each element are added for
+// q = 0 .. G-1.  n % 4 == 0 and part 16-byte aligned.
+template <int G>
 __global__ __launch_bounds__(256) void k_sum_chunks(const float *__restrict__ part, int64_t n, int nchunk,
                                                     float *__restrict__ out, int accumulate)
 {
-    __shared__ float red[8][32];
-    const int e = threadIdx.x & 31, q = threadIdx.x >> 5;
-    const int64_t i = (int64_t)blockIdx.x * 32 + e;
-    float s = 0.0f;
-    if (i < n) {
-#pragma unroll 8
-        for (int c = q; c < nchunk; c += 8) s += part[(int64_t)c * n + i];
+    constexpr int E4 = 256 / G;
+    __shared__ float red[G][4 * E4 + 1];
+    const int e4 = threadIdx.x % E4, q = threadIdx.x / E4;
+    const int64_t i4 = ((int64_t)blockIdx.x * E4 + e4) * 4;
+    float4 s = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (i4 < n) {
+#pragma unroll 4
+        for (int c = q; c < nchunk; c += G) {
+            const float4 v = *(const float4 *)(part + (int64_t)c * n + i4);
+            s.x += v.x;
+            s.y += v.y;
+            s.z += v.z;
+            s.w += v.w;
+        }
     }
-    red[q][e] = s;
+    red[q][4 * e4] = s.x;
+    red[q][4 * e4 + 1] = s.y;
+    red[q][4 * e4 + 2] = s.z;
+    red[q][4 * e4 + 3] = s.w;
     __syncthreads();
-    if (q == 0 && i < n) {
+    const int e = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 4 * E4 + e;
+    if (e < 4 * E4 && i < n) {
         float t = red[0][e];
 #pragma unroll
-        for (int k = 1; k < 8; ++k) t += red[k][e];
+        for (int k = 1; k < G; ++k) t += red[k][e];
         out[i] = accumulate ? out[i] + t : t;
     }
 }
@@ -700,8 +765,30 @@ __global__ void k_cavity_fields(const __bf16 *__restrict__ out, int o_cs, const 
 
 inline int blocks_for(int64_t n, int t = 256) { return (int)((n + t - 1) / t); }
 
+// Fixed-order sum of nchunk partial vectors of n floats (n % 4 == 0, 16-byte aligned).
+void sum_chunks(const float *part, int64_t n, int nchunk, float *out, int accumulate, hipStream_t st)
+{
+    if (nchunk >= 128)
+        hipLaunchKernelGGL(k_sum_chunks<32>, dim3(blocks_for(n, 32)), dim3(256), 0, st, part, n, nchunk, out,
+                           accumulate);
+    else
+        hipLaunchKernelGGL(k_sum_chunks<8>, dim3(blocks_for(n, 128)), dim3(256), 0, st, part, n, nchunk, out,
+                           accumulate);
+}
+
 constexpr int64_t kWgradWaves = 8192;    // target single-wave workgroups of the gather kernel
-constexpr int64_t kWgradGroups = 768;    // target three-wave workgroups of the LDS-staged kernel
+// LDS-staged weight gradient: split over pixels into about kWgradGroups three-wave
+// workgroups, but with the split-K partials (written once, read once by the sum) held
+// to kWgradPartFrac of the bytes the workgroups read.  Deep layers have few pixels and
+// large 9 x Cout x Cin partials, so there the cap, not the fill target, sets the split.
+#ifndef DDF_WGRAD_GROUPS
+#define DDF_WGRAD_GROUPS 768
+#endif
+#ifndef DDF_WGRAD_PART_FRAC
+#define DDF_WGRAD_PART_FRAC 1e30
+#endif
+constexpr int64_t kWgradGroups = DDF_WGRAD_GROUPS;
+constexpr double kWgradPartFrac = DDF_WGRAD_PART_FRAC;
 
 int check_launch()
 {
@@ -772,8 +859,13 @@ WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout)
         P.ci_t = Cin % 64 == 0 ? 2 : 1;
         const int64_t groups = (int64_t)(Cin / (32 * P.ci_t)) * (Cout / (32 * P.co_t));
         const int64_t nblocks = npix / P.pb;
+        // bytes read: each workgroup stages its input-channel and output-channel slices
+        const double reads = 2.0 * (double)npix *
+                             ((double)Cin * (Cout / (32 * P.co_t)) + (double)Cout * (Cin / (32 * P.ci_t)));
+        const double part_chunk = 4.0 * ((double)9 * Cout * Cin + Cout);
+        const int64_t cap = std::max<int64_t>(1, (int64_t)std::min(kWgradPartFrac * reads / part_chunk, 1e15));
         int64_t nchunk = (kWgradGroups + groups - 1) / groups;
-        nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, nblocks));
+        nchunk = std::max<int64_t>(1, std::min<int64_t>({nchunk, cap, nblocks}));
         P.per_chunk = (nblocks + nchunk - 1) / nchunk;
         P.nchunk = (nblocks + P.per_chunk - 1) / P.per_chunk;
     } else {
@@ -829,7 +921,8 @@ int ddf_nn_conv3x3_wgrad(const void *in, int32_t N, int32_t H, int32_t W, int32_
     if (N <= 0 || H <= 0 || W <= 0) return fail(DDF_ERR_ARG, "wgrad: bad shape");
     if (Cin % 32 || Cout % 32) return fail(DDF_ERR_ARG, "wgrad: Cin and Cout must be multiples of 32");
     if (Cout > 256) return fail(DDF_ERR_ARG, "wgrad: Cout must be at most 256");
-    if (((uintptr_t)in | (uintptr_t)dout) & 15) return fail(DDF_ERR_ARG, "wgrad: tensors must be 16-byte aligned");
+    if (((uintptr_t)in | (uintptr_t)dout | (uintptr_t)workspace) & 15)
+        return fail(DDF_ERR_ARG, "wgrad: tensors and workspace must be 16-byte aligned");
     if (in_cs % 8 || in_co % 8 || d_cs % 8 || in_cs < in_co + Cin || d_cs < Cout)
         return fail(DDF_ERR_ARG, "wgrad: channel strides and offsets must be multiples of 8 and cover the channels");
     hipStream_t st = (hipStream_t)stream;
@@ -843,22 +936,17 @@ int ddf_nn_conv3x3_wgrad(const void *in, int32_t N, int32_t H, int32_t W, int32_
         if (P.pb == 64) launch_wgrad_lds<64>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, st);
         else if (P.pb == 32) launch_wgrad_lds<32>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, st);
         else launch_wgrad_lds<16>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, st);
-        hipLaunchKernelGGL(k_sum_chunks, dim3(blocks_for(wsz, 32)), dim3(256), 0, st, part, wsz, (int)P.nchunk, dw,
-                           accumulate);
-        if (db)
-            hipLaunchKernelGGL(k_sum_chunks, dim3(blocks_for(Cout, 32)), dim3(256), 0, st, bpart, (int64_t)Cout,
-                               (int)P.nchunk, db, accumulate);
+        sum_chunks(part, wsz, (int)P.nchunk, dw, accumulate, st);
+        if (db) sum_chunks(bpart, (int64_t)Cout, (int)P.nchunk, db, accumulate, st);
         return check_launch();
     }
     hipLaunchKernelGGL(k_conv3x3_wgrad, dim3((Cin / 32) * (Cout / 32), 9, (unsigned)P.nchunk), dim3(64), 0, st, ib, N, H,
                        W, Cin, in_cs, in_co, db16, Cout, d_cs, (int)P.per_chunk, part);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(blocks_for(wsz, 32)), dim3(256), 0, st, part, wsz, (int)P.nchunk, dw,
-                       accumulate);
+    sum_chunks(part, wsz, (int)P.nchunk, dw, accumulate, st);
     if (db) {
         const int nb = (int)((npix + 255) / 256);
         hipLaunchKernelGGL(k_bias_grad, dim3(nb), dim3(256), 0, st, db16, (int)npix, Cout, d_cs, part);
-        hipLaunchKernelGGL(k_sum_chunks, dim3(blocks_for(Cout, 32)), dim3(256), 0, st, part, (int64_t)Cout, nb, db,
-                           accumulate);
+        sum_chunks(part, (int64_t)Cout, nb, db, accumulate, st);
     }
     return check_launch();
 }

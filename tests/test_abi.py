@@ -91,3 +91,19 @@ def test_step_before_init_is_a_state_error():
         assert L.lib().ddf_reduce(h, buf, None) == L.DDF_ERR_STATE
     finally:
         L.lib().ddf_destroy(h)
+
+
+def test_weight_gradient_rejects_bad_arguments_before_any_launch():
+    lib = L.lib()
+    a, b, w = C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20)
+    dw, db = C.cast(C.c_void_p(4 << 20), C.POINTER(C.c_float)), C.cast(C.c_void_p(5 << 20), C.POINTER(C.c_float))
+    cases = [
+        ((a, 1, 8, 8, 32, 32, 0, b, 32, 32, dw, db, 0, C.c_void_p(3 << 20 | 4), None), "aligned"),
+        ((C.c_void_p(1 << 20 | 8), 1, 8, 8, 32, 32, 0, b, 32, 32, dw, db, 0, w, None), "aligned"),
+        ((a, 1, 8, 8, 48, 48, 0, b, 32, 32, dw, db, 0, w, None), "multiples of 32"),
+        ((a, 1, 8, 8, 32, 32, 0, b, 288, 288, dw, db, 0, w, None), "at most 256"),
+        ((a, 1, 8, 8, 32, 36, 0, b, 32, 32, dw, db, 0, w, None), "multiples of 8"),
+    ]
+    for args, needle in cases:
+        assert lib.ddf_nn_conv3x3_wgrad(*args) == L.DDF_ERR_ARG
+        assert needle in lib.ddf_last_error().decode()
