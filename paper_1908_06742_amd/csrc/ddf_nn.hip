@@ -714,23 +714,40 @@ __global__ void k_cast_weights(const float *__restrict__ w, int Cout, int Cin, i
 // Network input for lid-driven cavities: channel 0 wall mask (1 next to a fixed wall,
 // 2 next to the lid), channel 1 (log Re - log Re_lo) / (log Re_hi - log Re_lo), channel
 // 2 U / U_ref, channels 3..C-1 zero.  re, u: per-sample values.
-__global__ void k_cavity_inputs(const float *__restrict__ re, const float *__restrict__ u, int N, int H, int W, int C,
-                                float lre_lo, float lre_hi, float u_ref, __bf16 *__restrict__ x)
+__device__ __forceinline__ float cavity_channel(int c, int px, int py, int W, int H, float lre, float un)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)N * H * W) return;
-    const int px = i % W, py = (i / W) % H, n = i / ((int64_t)W * H);
-    float mask = (px == 0 || px == W - 1 || py == 0) ? 1.0f : 0.0f;
-    if (py == H - 1) mask = 2.0f;
-    __bf16 *o = x + i * C;
-    o[0] = (__bf16)mask;
-    o[1] = (__bf16)((logf(re[n]) - lre_lo) / (lre_hi - lre_lo));
-    o[2] = (__bf16)(u[n] / u_ref);
+    switch (c) {
+    case 0: return py == H - 1 ? 2.0f : ((px == 0 || px == W - 1 || py == 0) ? 1.0f : 0.0f);   // lid 2, walls 1
+    case 1: return lre;
+    case 2: return un;
     // node coordinates in [0, 1]: the receptive field of the network is smaller than
     // the cavity, so position is an input rather than something inferred from walls
-    o[3] = (__bf16)(W > 1 ? (float)px / (float)(W - 1) : 0.0f);
-    o[4] = (__bf16)(H > 1 ? (float)py / (float)(H - 1) : 0.0f);
-    for (int c = 5; c < C; ++c) o[c] = (__bf16)0.0f;
+    case 3: return W > 1 ? (float)px / (float)(W - 1) : 0.0f;
+    case 4: return H > 1 ? (float)py / (float)(H - 1) : 0.0f;
+    default: return 0.0f;
+    }
+}
+
+// One thread per (pixel, group of 8 channels) writing 16 bytes (C % 8 == 0, x 16-byte
+// aligned), or per pixel with single stores (vec == 0).
+__global__ void k_cavity_inputs(const float *__restrict__ re, const float *__restrict__ u, int N, int H, int W, int C,
+                                float lre_lo, float lre_hi, float u_ref, __bf16 *__restrict__ x, int vec)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = vec ? C / 8 : 1;
+    if (i >= (int64_t)N * H * W * per) return;
+    const int64_t pix = i / per;
+    const int grp = (int)(i - pix * per);
+    const int px = pix % W, py = (pix / W) % H, n = pix / ((int64_t)W * H);
+    const float lre = (logf(re[n]) - lre_lo) / (lre_hi - lre_lo), un = u[n] / u_ref;
+    if (vec) {
+        bf16x8 v;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = (__bf16)cavity_channel(8 * grp + k, px, py, W, H, lre, un);
+        store8(x + pix * C + 8 * grp, v);
+    } else {
+        for (int c = 0; c < C; ++c) x[pix * C + c] = (__bf16)cavity_channel(c, px, py, W, H, lre, un);
+    }
 }
 
 // Normalised training targets from steady fields (dense FP64 [N][H][W] each):
@@ -785,7 +802,7 @@ constexpr int64_t kWgradWaves = 8192;    // target single-wave workgroups of the
 #define DDF_WGRAD_GROUPS 768
 #endif
 #ifndef DDF_WGRAD_PART_FRAC
-#define DDF_WGRAD_PART_FRAC 1e30
+#define DDF_WGRAD_PART_FRAC 1.0
 #endif
 constexpr int64_t kWgradGroups = DDF_WGRAD_GROUPS;
 constexpr double kWgradPartFrac = DDF_WGRAD_PART_FRAC;
@@ -1064,8 +1081,9 @@ int ddf_nn_cavity_inputs(const float *re, const float *u, int32_t N, int32_t H, 
 {
     if (C < 5) return fail(DDF_ERR_ARG, "cavity_inputs: at least 5 channels");
     if (N < 0 || H < 1 || W < 1) return fail(DDF_ERR_ARG, "cavity_inputs: bad shape");
-    hipLaunchKernelGGL(k_cavity_inputs, dim3(blocks_for((int64_t)N * H * W)), dim3(256), 0, (hipStream_t)stream, re, u, N,
-                       H, W, C, std::log(re_lo), std::log(re_hi), u_ref, (__bf16 *)x);
+    const int vec = C % 8 == 0 && al16(x);
+    hipLaunchKernelGGL(k_cavity_inputs, dim3(blocks_for((int64_t)N * H * W * (vec ? C / 8 : 1))), dim3(256), 0,
+                       (hipStream_t)stream, re, u, N, H, W, C, std::log(re_lo), std::log(re_hi), u_ref, (__bf16 *)x, vec);
     return check_launch();
 }
 

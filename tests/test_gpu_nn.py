@@ -247,13 +247,16 @@ def test_training_reduces_loss():
     assert losses[-1] < 0.2 * losses[0], (losses[0], losses[-1])
 
 
-def test_cavity_input_channels():
+@pytest.mark.parametrize("C,off", [(32, 0), (13, 0), (32, 2)])   # 16-byte stores; single stores (C % 8, unaligned)
+def test_cavity_input_channels(C, off):
     B, H, W = 2, 16, 24
     re = torch.tensor([100.0, 5000.0], device=DEV)
     u = torch.tensor([0.05, 0.1], device=DEV)
-    x = torch.empty(B * H * W * 32, dtype=torch.bfloat16, device=DEV)
-    L.check(L.lib().ddf_nn_cavity_inputs(p(re), p(u), B, H, W, 32, 100.0, 5000.0, 0.1, p(x), s0()))
-    a = np_of(x, (B, H, W, 32))
+    buf = torch.full((off + B * H * W * C,), 7.0, dtype=torch.bfloat16, device=DEV)
+    x = buf[off:]
+    L.check(L.lib().ddf_nn_cavity_inputs(p(re), p(u), B, H, W, C, 100.0, 5000.0, 0.1, p(x), s0()))
+    a = np_of(x, (B, H, W, C))
+    assert np.all(np_of(buf[:off], (off,)) == 7.0)
     yy, xx = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
     mask = np.where((xx == 0) | (xx == W - 1) | (yy == 0), 1.0, 0.0)
     mask[H - 1, :] = 2.0
