@@ -79,6 +79,19 @@ int ddf_nn_adam(float *w, const float *g, float *m, float *v, int64_t n, float l
  * wd[9][Cin_p][Cout_p] used for the data gradient; padding entries are zero. */
 int ddf_nn_cast_weights(const float *w, int32_t Cout, int32_t Cin, int32_t Cout_p, int32_t Cin_p, void *wf, void *wd,
                         void *stream);
+/* One layer of ddf_nn_cast_weights_multi: the arguments of ddf_nn_cast_weights (device
+ * pointers; wd may be NULL). */
+typedef struct {
+    const float *w;
+    void *wf;
+    void *wd;
+    int32_t Cout, Cin, Cout_p, Cin_p;
+} ddf_nn_cast_layer;
+#define DDF_NN_CAST_MAX_LAYERS 32
+/* ddf_nn_cast_weights for n layers (1 <= n <= DDF_NN_CAST_MAX_LAYERS, else DDF_ERR_ARG) in
+ * one launch: a network's casts after each optimizer step.  `layers` is a host array,
+ * read during the call (passed to the kernel by value). */
+int ddf_nn_cast_weights_multi(int32_t n, const ddf_nn_cast_layer *layers, void *stream);
 
 /* Lid-driven cavity inputs [N][H][W][C], C >= 5: wall mask (1 next to a fixed wall, 2 next
  * to the lid at y = H - 1), (log Re - log re_lo) / (log re_hi - log re_lo), U / u_ref,

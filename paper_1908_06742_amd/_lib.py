@@ -98,6 +98,15 @@ SIGNATURES = {
 _i32, _i64, _f32 = C.c_int32, C.c_int64, C.c_float
 _fp = C.POINTER(C.c_float)
 _dp = C.POINTER(C.c_double)
+NN_CAST_MAX_LAYERS = 32
+
+
+class CastLayer(C.Structure):
+    """ddf_nn_cast_layer (include/ddf_nn.h)."""
+    _fields_ = [("w", C.c_void_p), ("wf", C.c_void_p), ("wd", C.c_void_p),
+                ("Cout", C.c_int32), ("Cin", C.c_int32), ("Cout_p", C.c_int32), ("Cin_p", C.c_int32)]
+
+
 NN_SIGNATURES = {
     "ddf_nn_conv3x3": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32,
                                  _vp]),
@@ -114,6 +123,7 @@ NN_SIGNATURES = {
     "ddf_nn_mse": (C.c_int, [_vp, _i32, _vp, _i64, _fp, _vp, _vp, _vp, _vp]),
     "ddf_nn_adam": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _i64, _f32, _vp]),
     "ddf_nn_cast_weights": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp]),
+    "ddf_nn_cast_weights_multi": (C.c_int, [_i32, C.POINTER(CastLayer), _vp]),
     "ddf_nn_cavity_inputs": (C.c_int, [_vp, _vp, _i32, _i32, _i32, _i32, _f32, _f32, _f32, _vp, _vp]),
     "ddf_nn_cavity_targets": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp]),
     "ddf_nn_cavity_fields": (C.c_int, [_vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),

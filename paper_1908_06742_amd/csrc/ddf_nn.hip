@@ -698,17 +698,41 @@ __global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float
 
 // FP32 master weight w[9][Cout][Cin] -> BF16 forward copy wf[9][Cout_p][Cin_p] and the
 // tap-flipped transpose for the data gradient wd[9][Cin_p][Cout_p] (zero padding).
-__global__ void k_cast_weights(const float *__restrict__ w, int Cout, int Cin, int Cout_p, int Cin_p,
-                               __bf16 *__restrict__ wf, __bf16 *__restrict__ wd)
+__device__ __forceinline__ void cast_one(const float *__restrict__ w, int Cout, int Cin, int Cout_p, int Cin_p,
+                                         __bf16 *__restrict__ wf, __bf16 *__restrict__ wd, int64_t i)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)9 * Cout_p * Cin_p) return;
     const int ci = i % Cin_p;
     const int co = (i / Cin_p) % Cout_p;
     const int tap = i / ((int64_t)Cin_p * Cout_p);
     const float v = (co < Cout && ci < Cin) ? w[((int64_t)tap * Cout + co) * Cin + ci] : 0.0f;
     wf[i] = (__bf16)v;
     if (wd) wd[((int64_t)(8 - tap) * Cin_p + ci) * Cout_p + co] = (__bf16)v;
+}
+
+__global__ void k_cast_weights(const float *__restrict__ w, int Cout, int Cin, int Cout_p, int Cin_p,
+                               __bf16 *__restrict__ wf, __bf16 *__restrict__ wd)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)9 * Cout_p * Cin_p) return;
+    cast_one(w, Cout, Cin, Cout_p, Cin_p, wf, wd, i);
+}
+
+// Several layers in one launch: element i belongs to the layer k with start[k] <= i <
+// start[k + 1] (start[k] = sum of 9 Cout_p Cin_p over the layers before k).
+struct CastTable {
+    ddf_nn_cast_layer l[DDF_NN_CAST_MAX_LAYERS];
+    int64_t start[DDF_NN_CAST_MAX_LAYERS + 1];
+    int n;
+};
+
+__global__ void k_cast_weights_multi(const CastTable t)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= t.start[t.n]) return;
+    int k = 0;
+    while (k + 1 < t.n && i >= t.start[k + 1]) ++k;
+    const ddf_nn_cast_layer &L = t.l[k];
+    cast_one(L.w, L.Cout, L.Cin, L.Cout_p, L.Cin_p, (__bf16 *)L.wf, (__bf16 *)L.wd, i - t.start[k]);
 }
 
 // Network input for lid-driven cavities: channel 0 wall mask (1 next to a fixed wall,
@@ -1073,6 +1097,25 @@ int ddf_nn_cast_weights(const float *w, int32_t Cout, int32_t Cin, int32_t Cout_
     if (Cout_p < Cout || Cin_p < Cin) return fail(DDF_ERR_ARG, "cast_weights: padded sizes smaller than the real ones");
     hipLaunchKernelGGL(k_cast_weights, dim3(blocks_for((int64_t)9 * Cout_p * Cin_p)), dim3(256), 0, (hipStream_t)stream,
                        w, Cout, Cin, Cout_p, Cin_p, (__bf16 *)wf, (__bf16 *)wd);
+    return check_launch();
+}
+
+int ddf_nn_cast_weights_multi(int32_t n, const ddf_nn_cast_layer *layers, void *stream)
+{
+    if (n < 1 || n > DDF_NN_CAST_MAX_LAYERS || !layers)
+        return fail(DDF_ERR_ARG, "cast_weights_multi: need 1 to DDF_NN_CAST_MAX_LAYERS layers");
+    CastTable t{};
+    t.n = n;
+    t.start[0] = 0;
+    for (int k = 0; k < n; ++k) {
+        const ddf_nn_cast_layer &L = layers[k];
+        if (!L.w || !L.wf || L.Cout < 1 || L.Cin < 1 || L.Cout_p < L.Cout || L.Cin_p < L.Cin)
+            return fail(DDF_ERR_ARG, "cast_weights_multi: layer " + std::to_string(k) +
+                                         " has a null pointer or padded sizes smaller than the real ones");
+        t.l[k] = L;
+        t.start[k + 1] = t.start[k] + (int64_t)9 * L.Cout_p * L.Cin_p;
+    }
+    hipLaunchKernelGGL(k_cast_weights_multi, dim3(blocks_for(t.start[n])), dim3(256), 0, (hipStream_t)stream, t);
     return check_launch();
 }
 

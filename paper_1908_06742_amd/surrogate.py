@@ -112,10 +112,17 @@ class UNet:
         return C.c_void_p(s.cuda_stream)
 
     def cast(self):
-        for name, ci, co, _ in self.table:
-            _, _, cip, cop, _ = self._dims(name)
-            L.check(L.lib().ddf_nn_cast_weights(self._wptr(self.w, name), cop, cip, cop, cip, _p(self.wf[name]),
-                                                _p(self.wd[name]), self._s()))
+        """BF16 forward and data-gradient copies of every layer, one launch per 32 layers."""
+        if getattr(self, "_cast_layers", None) is None:
+            rows = []
+            for name, ci, co, _ in self.table:
+                _, _, cip, cop, _ = self._dims(name)
+                rows.append(L.CastLayer(self._wptr(self.w, name).value, self.wf[name].data_ptr(),
+                                        self.wd[name].data_ptr(), cop, cip, cop, cip))
+            self._cast_layers = [(L.CastLayer * len(rows[i:i + L.NN_CAST_MAX_LAYERS]))(*rows[i:i + L.NN_CAST_MAX_LAYERS])
+                                 for i in range(0, len(rows), L.NN_CAST_MAX_LAYERS)]
+        for arr in self._cast_layers:
+            L.check(L.lib().ddf_nn_cast_weights_multi(len(arr), arr, self._s()))
 
     def state_dict(self):
         return {"w": self.w.detach().cpu().numpy(), "base": self.base, "levels": self.levels}

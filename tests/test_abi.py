@@ -107,3 +107,15 @@ def test_weight_gradient_rejects_bad_arguments_before_any_launch():
     for args, needle in cases:
         assert lib.ddf_nn_conv3x3_wgrad(*args) == L.DDF_ERR_ARG
         assert needle in lib.ddf_last_error().decode()
+
+
+def test_cast_weights_multi_rejects_bad_tables_before_any_launch():
+    lib = L.lib()
+    ok = L.CastLayer(1 << 20, 2 << 20, 3 << 20, 32, 32, 32, 32)
+    for n in (0, L.NN_CAST_MAX_LAYERS + 1):
+        arr = (L.CastLayer * max(n, 1))(*([ok] * max(n, 1)))
+        assert lib.ddf_nn_cast_weights_multi(n, arr, None) == L.DDF_ERR_ARG
+    for bad in (L.CastLayer(None, 2 << 20, None, 32, 32, 32, 32), L.CastLayer(1 << 20, 2 << 20, None, 64, 32, 32, 32)):
+        arr = (L.CastLayer * 2)(ok, bad)
+        assert lib.ddf_nn_cast_weights_multi(2, arr, None) == L.DDF_ERR_ARG
+        assert "layer 1" in lib.ddf_last_error().decode()

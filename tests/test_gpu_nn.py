@@ -129,6 +129,32 @@ def test_pool_up_slice_relu_kernels():
     assert np.array_equal(np_of(gg, x.shape), np.where(x > 0, x, 0.0))
 
 
+def test_cast_weights_multi_matches_per_layer_casts():
+    # padded and unpadded layers, one without the data-gradient copy
+    shapes = [(32, 5, 32, 32, True), (64, 32, 64, 32, True), (96, 40, 96, 64, False), (256, 256, 256, 256, True)]
+    r = np.random.default_rng(7)
+    layers, ref = [], []
+    for co, ci, cop, cip, with_wd in shapes:
+        w = torch.tensor(r.standard_normal(9 * co * ci), dtype=torch.float32, device=DEV)
+        bufs = [torch.full((9 * cop * cip,), 3.0, dtype=torch.bfloat16, device=DEV) for _ in range(4)]
+        wd1, wd2 = (bufs[1], bufs[3]) if with_wd else (None, None)
+        L.check(L.lib().ddf_nn_cast_weights(p(w), co, ci, cop, cip, p(bufs[0]), p(wd1) if wd1 is not None else None,
+                                            s0()))
+        layers.append(L.CastLayer(w.data_ptr(), bufs[2].data_ptr(), wd2.data_ptr() if wd2 is not None else None,
+                                  co, ci, cop, cip))
+        ref.append((w, bufs, with_wd))
+    arr = (L.CastLayer * len(layers))(*layers)
+    L.check(L.lib().ddf_nn_cast_weights_multi(len(layers), arr, s0()))
+    torch.cuda.synchronize()
+    for (co, ci, cop, cip, with_wd), (w, bufs, _) in zip(shapes, ref):
+        assert torch.equal(bufs[0], bufs[2])
+        assert torch.equal(bufs[1], bufs[3])
+        if not with_wd:
+            assert torch.all(bufs[3].float() == 3.0)
+        wf = bufs[2].float().cpu().numpy().reshape(9, cop, cip)
+        assert np.all(wf[:, co:, :] == 0) and np.all(wf[:, :, ci:] == 0)
+
+
 def test_mse_and_adam():
     r = np.random.default_rng(11)
     npix = 4 * 16 * 16
