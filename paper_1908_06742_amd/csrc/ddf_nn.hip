@@ -259,14 +259,15 @@ __device__ __forceinline__ bf16x8 tr_operand(const __bf16 *p, int row_stride)
 // and its CO_T x CI_T output tiles of 32 x 32, so each staged value feeds several MFMAs.
 // The contraction runs over pixels, which NHWC keeps strided: operands come out of the
 // [pixel][channel] tiles by transpose reads (tr_operand); rows are padded by 8 elements.
-// part[chunk][tap][co][ci] receives the chunk's sums (tap = 3 (dy + 1) + dx + 1).  The
-// workgroups of the first input-channel tile also sum the staged output gradient over
-// the chunk's pixels into bpart[chunk][co] (bias gradient), in a fixed order.
+// part[chunk * cstride + (tap Cout + co) Cin + ci] receives the chunk's sums (tap =
+// 3 (dy + 1) + dx + 1).  The workgroups of the first input-channel tile also sum the
+// staged output gradient over the chunk's pixels into bpart[chunk * cstride + co] (bias
+// gradient), in a fixed order.
 template <int PB, int CO_T, int CI_T>
 __global__ __launch_bounds__(192) void k_wgrad_lds(const __bf16 *__restrict__ in, int N, int H, int W, int Cin,
                                                    int in_cs, int in_co, const __bf16 *__restrict__ dout, int Cout,
                                                    int d_cs, int blocks_per_chunk, float *__restrict__ part,
-                                                   float *__restrict__ bpart)
+                                                   float *__restrict__ bpart, int64_t cstride)
 {
     constexpr int XS = 32 * CI_T + 8;
     constexpr int DS = 32 * CO_T + 8;
@@ -375,12 +376,12 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(const __bf16 *__restrict__ in
             const int c8 = tid >> 3, i = tid & 7;
             float t = 0.0f;
             for (int u = c8; u < 192; u += 4 * CO_T) t += bred[u][i];
-            bpart[(int64_t)ck * Cout + co0 + 8 * c8 + i] = t;
+            bpart[(int64_t)ck * cstride + co0 + 8 * c8 + i] = t;
         }
     }
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
-        float *o = part + (((int64_t)ck * 9 + 3 * r + dx) * Cout) * Cin;
+        float *o = part + (int64_t)ck * cstride + ((int64_t)(3 * r + dx) * Cout) * Cin;
 #pragma unroll
         for (int t = 0; t < CO_T; ++t)
 #pragma unroll
@@ -393,14 +394,16 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(const __bf16 *__restrict__ in
     }
 }
 
-// out[i] (= or +=) sum_c part[c][i] over c = 0 .. nchunk-1, in a fixed order: a block of
-// 256 threads covers 4 (256 / G) elements, as 256 / G groups of 4 consecutive elements
-// (one 16-byte load) x G chunk groups; thread (e4, q) sums the chunks c = q, q + G, ...
-// of its 4 elements in increasing c, then the G group sums of each element are added for
-// q = 0 .. G-1.  n % 4 == 0 and part 16-byte aligned.
+// s[i] = sum_c part[c * stride + i] over c = 0 .. nchunk-1 for i < n, in a fixed order:
+// a block of 256 threads covers 4 (256 / G) elements, as 256 / G groups of 4 consecutive
+// elements (one 16-byte load) x G chunk groups; thread (e4, q) sums the chunks c = q,
+// q + G, ... of its 4 elements in increasing c, then the G group sums of each element are
+// added for q = 0 .. G-1.  s[i] goes to out[i] for i < na and to out_b[i - na] after
+// (= or += with accumulate).  n, stride and na multiples of 4, part 16-byte aligned.
 template <int G>
-__global__ __launch_bounds__(256) void k_sum_chunks(const float *__restrict__ part, int64_t n, int nchunk,
-                                                    float *__restrict__ out, int accumulate)
+__global__ __launch_bounds__(256) void k_sum_chunks(const float *__restrict__ part, int64_t n, int64_t stride,
+                                                    int nchunk, float *__restrict__ out, int64_t na,
+                                                    float *__restrict__ out_b, int accumulate)
 {
     constexpr int E4 = 256 / G;
     __shared__ float red[G][4 * E4 + 1];
@@ -410,7 +413,7 @@ __global__ __launch_bounds__(256) void k_sum_chunks(const float *__restrict__ pa
     if (i4 < n) {
 #pragma unroll 4
         for (int c = q; c < nchunk; c += G) {
-            const float4 v = *(const float4 *)(part + (int64_t)c * n + i4);
+            const float4 v = *(const float4 *)(part + (int64_t)c * stride + i4);
             s.x += v.x;
             s.y += v.y;
             s.z += v.z;
@@ -428,7 +431,8 @@ __global__ __launch_bounds__(256) void k_sum_chunks(const float *__restrict__ pa
         float t = red[0][e];
 #pragma unroll
         for (int k = 1; k < G; ++k) t += red[k][e];
-        out[i] = accumulate ? out[i] + t : t;
+        float *o = i < na ? out + i : out_b + (i - na);
+        *o = accumulate ? *o + t : t;
     }
 }
 
@@ -806,15 +810,17 @@ __global__ void k_cavity_fields(const __bf16 *__restrict__ out, int o_cs, const 
 
 inline int blocks_for(int64_t n, int t = 256) { return (int)((n + t - 1) / t); }
 
-// Fixed-order sum of nchunk partial vectors of n floats (n % 4 == 0, 16-byte aligned).
-void sum_chunks(const float *part, int64_t n, int nchunk, float *out, int accumulate, hipStream_t st)
+// Fixed-order sum of nchunk partial vectors of n floats, stride apart (n, stride and na
+// multiples of 4, 16-byte aligned); the first na sums go to out, the rest to out_b.
+void sum_chunks(const float *part, int64_t n, int64_t stride, int nchunk, float *out, int64_t na, float *out_b,
+                int accumulate, hipStream_t st)
 {
     if (nchunk >= 128)
-        hipLaunchKernelGGL(k_sum_chunks<32>, dim3(blocks_for(n, 32)), dim3(256), 0, st, part, n, nchunk, out,
-                           accumulate);
+        hipLaunchKernelGGL(k_sum_chunks<32>, dim3(blocks_for(n, 32)), dim3(256), 0, st, part, n, stride, nchunk, out,
+                           na, out_b, accumulate);
     else
-        hipLaunchKernelGGL(k_sum_chunks<8>, dim3(blocks_for(n, 128)), dim3(256), 0, st, part, n, nchunk, out,
-                           accumulate);
+        hipLaunchKernelGGL(k_sum_chunks<8>, dim3(blocks_for(n, 128)), dim3(256), 0, st, part, n, stride, nchunk, out,
+                           na, out_b, accumulate);
 }
 
 constexpr int64_t kWgradWaves = 8192;    // target single-wave workgroups of the gather kernel
@@ -924,13 +930,14 @@ WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout)
 
 template <int PB>
 int launch_wgrad_lds(const WgradPlan &P, const __bf16 *in, int N, int H, int W, int Cin, int in_cs, int in_co,
-                     const __bf16 *dout, int Cout, int d_cs, float *part, float *bpart, hipStream_t st)
+                     const __bf16 *dout, int Cout, int d_cs, float *part, float *bpart, int64_t cstride,
+                     hipStream_t st)
 {
     const dim3 grid((unsigned)((Cin / (32 * P.ci_t)) * (Cout / (32 * P.co_t))), (unsigned)P.nchunk);
     const int bpc = (int)P.per_chunk;
 #define DDF_WGRAD_LAUNCH(CO, CI)                                                                                   \
     hipLaunchKernelGGL((k_wgrad_lds<PB, CO, CI>), grid, dim3(192), 0, st, in, N, H, W, Cin, in_cs, in_co, dout, Cout, \
-                       d_cs, bpc, part, bpart)
+                       d_cs, bpc, part, bpart, cstride)
     if (P.co_t == 2 && P.ci_t == 2) DDF_WGRAD_LAUNCH(2, 2);
     else if (P.co_t == 2) DDF_WGRAD_LAUNCH(2, 1);
     else if (P.ci_t == 2) DDF_WGRAD_LAUNCH(1, 2);
@@ -973,21 +980,22 @@ int ddf_nn_conv3x3_wgrad(const void *in, int32_t N, int32_t H, int32_t W, int32_
     const __bf16 *ib = (const __bf16 *)in, *db16 = (const __bf16 *)dout;
     const int64_t wsz = (int64_t)9 * Cout * Cin;
     if (P.lds) {
-        float *bpart = db ? part + P.nchunk * wsz : nullptr;
-        if (P.pb == 64) launch_wgrad_lds<64>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, st);
-        else if (P.pb == 32) launch_wgrad_lds<32>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, st);
-        else launch_wgrad_lds<16>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, st);
-        sum_chunks(part, wsz, (int)P.nchunk, dw, accumulate, st);
-        if (db) sum_chunks(bpart, (int64_t)Cout, (int)P.nchunk, db, accumulate, st);
+        // chunk c holds its weight partials, then (with db) its bias partials
+        const int64_t cs = wsz + (db ? Cout : 0);
+        float *bpart = db ? part + wsz : nullptr;
+        if (P.pb == 64) launch_wgrad_lds<64>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, cs, st);
+        else if (P.pb == 32) launch_wgrad_lds<32>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, cs, st);
+        else launch_wgrad_lds<16>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, cs, st);
+        sum_chunks(part, cs, cs, (int)P.nchunk, dw, wsz, db, accumulate, st);
         return check_launch();
     }
     hipLaunchKernelGGL(k_conv3x3_wgrad, dim3((Cin / 32) * (Cout / 32), 9, (unsigned)P.nchunk), dim3(64), 0, st, ib, N, H,
                        W, Cin, in_cs, in_co, db16, Cout, d_cs, (int)P.per_chunk, part);
-    sum_chunks(part, wsz, (int)P.nchunk, dw, accumulate, st);
+    sum_chunks(part, wsz, wsz, (int)P.nchunk, dw, wsz, nullptr, accumulate, st);
     if (db) {
         const int nb = (int)((npix + 255) / 256);
         hipLaunchKernelGGL(k_bias_grad, dim3(nb), dim3(256), 0, st, db16, (int)npix, Cout, d_cs, part);
-        sum_chunks(part, (int64_t)Cout, nb, db, accumulate, st);
+        sum_chunks(part, (int64_t)Cout, (int64_t)Cout, nb, db, (int64_t)Cout, nullptr, accumulate, st);
     }
     return check_launch();
 }
