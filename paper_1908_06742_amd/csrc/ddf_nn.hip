@@ -902,8 +902,13 @@ WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout)
     P.pb = W % 64 == 0 ? 64 : (W % 32 == 0 ? 32 : (W % 16 == 0 ? 16 : 0));
     P.lds = P.pb > 0;
     if (P.lds) {
-        P.co_t = Cout % 64 == 0 ? 2 : 1;
-        P.ci_t = Cin % 64 == 0 ? 2 : 1;
+        // Two output-channel tiles per wavefront where there are pixels enough to fill the
+        // chip from the pixel split alone; on small images (at most 32768 pixels, 512 blocks
+        // of 64) single tiles win: more workgroups, and at 204 or fewer registers two
+        // wavefronts per SIMD.  Two input-channel tiles (336 registers, one wavefront per
+        // SIMD) measured slower at every layer size of the surrogate network.
+        P.co_t = npix > 32768 && Cout % 64 == 0 ? 2 : 1;
+        P.ci_t = 1;
         const int64_t groups = (int64_t)(Cin / (32 * P.ci_t)) * (Cout / (32 * P.co_t));
         const int64_t nblocks = npix / P.pb;
         // bytes read: each workgroup stages its input-channel and output-channel slices
@@ -938,9 +943,7 @@ int launch_wgrad_lds(const WgradPlan &P, const __bf16 *in, int N, int H, int W, 
 #define DDF_WGRAD_LAUNCH(CO, CI)                                                                                   \
     hipLaunchKernelGGL((k_wgrad_lds<PB, CO, CI>), grid, dim3(192), 0, st, in, N, H, W, Cin, in_cs, in_co, dout, Cout, \
                        d_cs, bpc, part, bpart, cstride)
-    if (P.co_t == 2 && P.ci_t == 2) DDF_WGRAD_LAUNCH(2, 2);
-    else if (P.co_t == 2) DDF_WGRAD_LAUNCH(2, 1);
-    else if (P.ci_t == 2) DDF_WGRAD_LAUNCH(1, 2);
+    if (P.co_t == 2) DDF_WGRAD_LAUNCH(2, 1);
     else DDF_WGRAD_LAUNCH(1, 1);
 #undef DDF_WGRAD_LAUNCH
     return DDF_OK;

@@ -298,10 +298,13 @@ def test_cavity_input_channels(C, off):
 
 
 @pytest.mark.parametrize("B,H,W,Cin,Cout", [
-    (1, 4, 64, 64, 64),      # 64-pixel blocks, 2 x 2 tiles
-    (1, 3, 128, 96, 32),     # 64-pixel blocks, 1 x 1 tiles (96 input channels)
-    (2, 5, 32, 32, 64),      # 32-pixel blocks, 2 x 1 tiles
-    (1, 2, 16, 128, 256),    # 16-pixel blocks, 2 x 2 tiles over 4 x 2 tile groups
+    (1, 4, 64, 64, 64),      # 64-pixel blocks, single 32 x 32 tiles (small image)
+    (1, 3, 128, 96, 32),     # 64-pixel blocks, single tiles (96 input channels)
+    (2, 5, 32, 32, 64),      # 32-pixel blocks, single tiles
+    (1, 2, 16, 128, 256),    # 16-pixel blocks, single tiles over 4 x 8 tile groups
+    (1, 129, 256, 32, 64),   # more than 32768 pixels: 64-pixel blocks, two output tiles per wavefront
+    (2, 17, 1024, 64, 128),  # two output tiles, 2 x 2 tile groups
+    (1, 1040, 32, 32, 64),   # 32-pixel blocks, two output tiles
     (2, 4, 8, 32, 32),       # rows of 8: the gather kernel
 ])
 def test_weight_gradient_kernels(B, H, W, Cin, Cout):
