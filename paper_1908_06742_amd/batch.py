@@ -55,7 +55,7 @@ class Batch:
         """fields: list of (rho, ux, uy, phi) per instance (arrays of shape (ny, nx))."""
         cat = []
         for k in range(4):
-            parts = [torch.as_tensor(np.ascontiguousarray(np.broadcast_to(np.asarray(f[k], np.float64), (p.ny, p.nx))))
+            parts = [torch.as_tensor(np.array(np.broadcast_to(np.asarray(f[k], np.float64), (p.ny, p.nx))))
                      .reshape(-1)
                      for f, p in zip(fields, self.problems)]
             cat.append(torch.cat(parts).to(self.device).contiguous())
@@ -75,7 +75,7 @@ class Batch:
 
         def dev(a):
             if not torch.is_tensor(a):
-                a = torch.as_tensor(np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), (p.ny, p.nx))))
+                a = torch.as_tensor(np.array(np.broadcast_to(np.asarray(a, np.float64), (p.ny, p.nx))))
             return a.to(self.device, torch.float64).contiguous()
 
         fields = [dev(a) for a in (rho, ux, uy, phi)]

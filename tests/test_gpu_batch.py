@@ -33,7 +33,17 @@ def mixed_problems(storage):
         (W.Problem(nx=100, ny=37, storage=storage, tau=0.6, tau_phi=0.65),
          W.VortexField(L=100, n_blobs=6, sigma=5.0, u_max=0.04).eval_grid(np.arange(100), np.arange(37))),
         (W.fourroll_problem(24, 0.01, 0.03).with_(storage=storage), W.fourroll_fields(24, 0.03)),
+        # the smallest instances: narrower and lower than any tile
+        (W.Problem(nx=2, ny=2, storage=storage), _random_fields(2, 2, 21)),
+        (W.cavity_problem(3, 10.0, 0.05, phi_lid=1.2, phi_walls=1.0, storage=storage).with_(ny=2),
+         _random_fields(3, 2, 22)),
     ]
+
+
+def _random_fields(nx, ny, seed):
+    r = np.random.default_rng(seed)
+    return (1.0 + 0.01 * r.standard_normal((ny, nx)), 0.02 * r.standard_normal((ny, nx)),
+            0.02 * r.standard_normal((ny, nx)), 1.0 + 0.1 * r.standard_normal((ny, nx)))
 
 
 def rel(a, b):

@@ -89,6 +89,12 @@ def test_fp64_taylor_green_1000_steps():
         assert rel(out[k], ref[k], field_scale(ref, k)) < 1e-10, k
 
 
+def _random_fields(nx, ny, seed):
+    r = np.random.default_rng(seed)
+    return (1.0 + 0.01 * r.standard_normal((ny, nx)), 0.02 * r.standard_normal((ny, nx)),
+            0.02 * r.standard_normal((ny, nx)), 1.0 + 0.1 * r.standard_normal((ny, nx)))
+
+
 def _channel_fields(nx, ny, umax):
     x, y = W.grid(nx, ny)
     yc = (y + 0.5 - ny / 2.0) / (ny / 2.0)
@@ -110,6 +116,10 @@ CASES = {
                               W.VortexField(L=300, n_blobs=8, sigma=6.0, u_max=0.05).eval_grid(np.arange(300), np.arange(19))),
     "zero_flux_walls": lambda: (W.cavity_problem(33, 100.0, 0.08, storage="f64").with_(wall_phi=(None, 0.5, None, 1.0)),
                                 W.rest_fields(33, 33, 1.0, 0.7)),
+    # the smallest lattices accepted: x - 1 and x + 1 are one node; every node is at a wall
+    "periodic_2x2": lambda: (W.Problem(nx=2, ny=2, storage="f64"), _random_fields(2, 2, 11)),
+    "cavity_3x2": lambda: (W.cavity_problem(3, 10.0, 0.05, phi_lid=1.2, phi_walls=1.0, storage="f64").with_(ny=2),
+                           _random_fields(3, 2, 12)),
 }
 
 
@@ -389,3 +399,41 @@ def test_graph_capture_refused_where_the_step_depends_on_time():
     with pytest.raises(DDFError, match="UNSUPPORTED"):
         lat.set_graph(20)
     lat.set_graph(0).step(3)
+
+
+def test_zero_steps_change_nothing():
+    say("case: zero steps")
+    pr, fields = CASES["cavity_ragged"]()
+    lat = Lattice(pr, device=DEV).init(*fields)
+    f0, g0 = (t.cpu().numpy() for t in lat.get_populations(raw=True))
+    lat.step(0)
+    f1, g1 = (t.cpu().numpy() for t in lat.get_populations(raw=True))
+    assert lat.step_count == 0
+    assert np.array_equal(f0, f1) and np.array_equal(g0, g1)
+    lat.step(3).step(0)
+    assert lat.step_count == 3
+
+
+def test_outputs_are_nan_where_phi_is_below_the_threshold():
+    # the paper's vorticity needs phi != 0: a scalar without background vanishes on grid
+    # lines, and the phi-dependent outputs there must be NaN, exactly where the oracle has them
+    say("case: phi below phi_min")
+    n = 32
+    x, y = W.grid(n, n)
+    phi = 0.1 * np.sin(2 * np.pi * x / n) * np.sin(2 * np.pi * y / n)
+    rho, ux, uy, _ = W.taylor_green_fields(n, 0.01)
+    pr = W.taylor_green_problem(n, storage="f64", phi_min=1e-3)
+    fields = (rho, ux, uy, phi)
+    _, _, _, out = gpu_run(pr, fields, 20)
+    _, _, _, ref = oracle_run(pr, fields, 20)
+    clear = np.abs(np.abs(ref["phi"]) - 1e-3) > 1e-9          # no node sits on the threshold
+    assert clear.all()
+    small = np.abs(ref["phi"]) < 1e-3
+    assert small.sum() > 100
+    for k in ("wz", "dxuy", "dyux"):
+        assert np.array_equal(np.isnan(out[k]), small), k
+        assert np.array_equal(np.isnan(ref[k]), small), k
+        m = ~small
+        assert rel(out[k][m], ref[k][m], field_scale(ref, k)) < 1e-10, k
+    for k in ("rho", "ux", "uy", "phi", "Sxx", "Syy", "Sxy"):
+        assert np.all(np.isfinite(out[k])), k
