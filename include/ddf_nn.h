@@ -30,10 +30,16 @@ extern "C" {
  * (or += when accumulate).  wt: bf16 [9][Cout][Cin] from ddf_nn_cast_weights; bias may be
  * NULL; relu = 1 applies max(., 0).  Requires Cin % 16 == 0, Cout % 32 == 0,
  * N*H*W % 32 == 0.  With the tap-flipped transposed weight (the `wd` copy) and the
- * output gradient as input, the same call computes the data gradient. */
+ * output gradient as input, the same call computes the data gradient.  mask (may be NULL,
+ * bf16, mask_cs >= mask_co + Cout): the value for (p, co) is set to zero where
+ * mask[p * mask_cs + mask_co + co] is not > 0, before it is added with accumulate.  With
+ * the forward input of a layer whose input is a ReLU output as the mask, the data
+ * gradient comes out multiplied by the ReLU's derivative (the ReLU adjoint is linear, so
+ * each contribution to a gradient can be masked on its own). */
 int ddf_nn_conv3x3(const void *in, int32_t N, int32_t H, int32_t W, int32_t Cin, int32_t in_cs, int32_t in_co,
                    const void *wt, const float *bias, void *out, int32_t Cout, int32_t out_cs, int32_t out_co,
-                   int32_t relu, int32_t accumulate, void *stream);
+                   int32_t relu, int32_t accumulate, const void *mask, int32_t mask_cs, int32_t mask_co,
+                   void *stream);
 
 /* Bytes of workspace ddf_nn_conv3x3_wgrad needs; *chunk receives its pixel chunk (pixels
  * per split-K partial). */
@@ -50,10 +56,11 @@ int ddf_nn_conv3x3_wgrad(const void *in, int32_t N, int32_t H, int32_t W, int32_
 
 /* grad[i] = 0 where act[i] <= 0 (n contiguous elements). */
 int ddf_nn_relu_bwd(void *grad, const void *act, int64_t n, void *stream);
-/* 2x2 average pooling (contiguous C channels) and its adjoint (din = or += dout / 4). */
+/* 2x2 average pooling (contiguous C channels) and its adjoint (din = or += dout / 4, each
+ * child's value set to zero where mask, laid out as din, is not > 0; mask may be NULL). */
 int ddf_nn_pool2(const void *in, int32_t N, int32_t H, int32_t W, int32_t C, void *out, void *stream);
-int ddf_nn_pool2_bwd(const void *dout, int32_t N, int32_t H, int32_t W, int32_t C, void *din, int32_t accumulate,
-                     void *stream);
+int ddf_nn_pool2_bwd(const void *dout, int32_t N, int32_t H, int32_t W, int32_t C, void *din, const void *mask,
+                     int32_t accumulate, void *stream);
 /* Nearest 2x upsampling of in (h x w, C contiguous channels) into a channel slice of out,
  * and its adjoint (sum of the four children) from a channel slice of dout. */
 int ddf_nn_up2(const void *in, int32_t N, int32_t h, int32_t w, int32_t C, void *out, int32_t out_cs, int32_t out_co,

@@ -45,7 +45,8 @@ template <int WM, int WN>
 __global__ __launch_bounds__(64 * WM * WN) void k_conv3x3(const __bf16 *__restrict__ in, int N, int H, int W, int Cin,
                                                           int in_cs, int in_co, const __bf16 *__restrict__ wt,
                                                           const float *__restrict__ bias, __bf16 *__restrict__ out,
-                                                          int Cout, int out_cs, int out_co, int relu, int accumulate)
+                                                          int Cout, int out_cs, int out_co, int relu, int accumulate,
+                                                          const __bf16 *__restrict__ mask, int mask_cs, int mask_co)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave % WM, wn = wave / WM;
@@ -78,6 +79,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_conv3x3(const __bf16 *__restri
         __bf16 *o = out + (int64_t)pr * out_cs + out_co + co;
         float v = acc[j] + bv;
         if (relu) v = fmaxf(v, 0.0f);
+        if (mask && !((float)mask[(int64_t)pr * mask_cs + mask_co + co] > 0.0f)) v = 0.0f;
         if (accumulate) v += (float)*o;
         *o = (__bf16)v;
     }
@@ -94,7 +96,8 @@ template <int PB, int NCO>
 __global__ __launch_bounds__(256) void k_conv3x3_lds(const __bf16 *__restrict__ in, int N, int H, int W, int Cin,
                                                      int in_cs, int in_co, const __bf16 *__restrict__ wt,
                                                      const float *__restrict__ bias, __bf16 *__restrict__ out,
-                                                     int Cout, int out_cs, int out_co, int relu, int accumulate)
+                                                     int Cout, int out_cs, int out_co, int relu, int accumulate,
+                                                     const __bf16 *__restrict__ mask, int mask_cs, int mask_co)
 {
     constexpr int PMT = PB / 32;                 // pixel tiles
     constexpr int TPW = PMT * NCO / 4;           // output tiles per wavefront
@@ -143,6 +146,24 @@ __global__ __launch_bounds__(256) void k_conv3x3_lds(const __bf16 *__restrict__ 
         }
     };
     fetch(0);
+    // The mask values of this lane's outputs, one bit each, loaded behind the first
+    // stage's loads so that their latency is shared with it.
+    uint32_t mbits[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        mbits[t] = 0xffffu;
+        if (mask) {
+            const int tile = wave * TPW + t, pm = tile % PMT, cn = tile / PMT;
+            const int co = co0 + 32 * cn + m;
+            uint32_t b = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int64_t pr = row * W + x0 + 32 * pm + 8 * (j >> 2) + 4 * half + (j & 3);
+                b |= ((float)mask[pr * mask_cs + mask_co + co] > 0.0f ? 1u : 0u) << j;
+            }
+            mbits[t] = b;
+        }
+    }
     for (int s = 0; s < nst; ++s) {
 #pragma unroll
         for (int i = 0; i < NXV; ++i) {
@@ -182,6 +203,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_lds(const __bf16 *__restrict__ 
             __bf16 *o = out + pr * out_cs + out_co + co;
             float v = acc[t][j] + bv;
             if (relu) v = fmaxf(v, 0.0f);
+            if (!((mbits[t] >> j) & 1u)) v = 0.0f;
             if (accumulate) v += (float)*o;
             *o = (__bf16)v;
         }
@@ -469,14 +491,15 @@ __global__ void k_pool2(const __bf16 *__restrict__ in, int N, int H, int W, int 
 }
 
 __global__ void k_pool2_bwd(const __bf16 *__restrict__ dout, int N, int H, int W, int C, __bf16 *__restrict__ din,
-                            int accumulate)
+                            const __bf16 *__restrict__ mask, int accumulate)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)N * H * W * C) return;
     const int c = i % C;
     const int64_t q = i / C;
     const int x = q % W, y = (q / W) % H, n = q / ((int64_t)W * H);
-    const float v = 0.25f * (float)dout[((int64_t)(n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
+    float v = 0.25f * (float)dout[((int64_t)(n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
+    if (mask && !((float)mask[i] > 0.0f)) v = 0.0f;
     din[i] = (__bf16)(accumulate ? (float)din[i] + v : v);
 }
 
@@ -555,7 +578,7 @@ __global__ void k_pool2_8(const __bf16 *__restrict__ in, int N, int H, int W, in
 }
 
 __global__ void k_pool2_bwd8(const __bf16 *__restrict__ dout, int N, int H, int W, int C, __bf16 *__restrict__ din,
-                             int accumulate)
+                             const __bf16 *__restrict__ mask, int accumulate)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int C8 = C / 8;
@@ -565,9 +588,11 @@ __global__ void k_pool2_bwd8(const __bf16 *__restrict__ dout, int N, int H, int 
     const int x = q % W, y = (q / W) % H, n = q / ((int64_t)W * H);
     const bf16x8 d = load8(dout + ((int64_t)(n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c);
     bf16x8 r = accumulate ? load8(din + q * C + c) : zero8();
+    const bf16x8 mk = mask ? load8(mask + q * C + c) : zero8();
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const float v = 0.25f * (float)d[k];
+        float v = 0.25f * (float)d[k];
+        if (mask && !((float)mk[k] > 0.0f)) v = 0.0f;
         r[k] = (__bf16)(accumulate ? (float)r[k] + v : v);
     }
     store8(din + q * C + c, r);
@@ -850,7 +875,7 @@ extern "C" {
 
 int ddf_nn_conv3x3(const void *in, int32_t N, int32_t H, int32_t W, int32_t Cin, int32_t in_cs, int32_t in_co,
                    const void *wt, const float *bias, void *out, int32_t Cout, int32_t out_cs, int32_t out_co,
-                   int32_t relu, int32_t accumulate, void *stream)
+                   int32_t relu, int32_t accumulate, const void *mask, int32_t mask_cs, int32_t mask_co, void *stream)
 {
     const int64_t npix = (int64_t)N * H * W;
     if (!in || !wt || !out || N <= 0 || H <= 0 || W <= 0) return fail(DDF_ERR_ARG, "conv3x3: bad tensor arguments");
@@ -858,6 +883,9 @@ int ddf_nn_conv3x3(const void *in, int32_t N, int32_t H, int32_t W, int32_t Cin,
         return fail(DDF_ERR_ARG, "conv3x3: need Cin % 16 == 0, Cout % 32 == 0, 8-aligned channel strides and offsets");
     if (npix % 32) return fail(DDF_ERR_ARG, "conv3x3: N*H*W must be a multiple of 32");
     if (npix > (int64_t)1 << 30) return fail(DDF_ERR_ARG, "conv3x3: too many pixels");
+    if (mask && (mask_co < 0 || mask_cs < mask_co + Cout))
+        return fail(DDF_ERR_ARG, "conv3x3: the mask's channel stride and offset must cover the output channels");
+    const __bf16 *mk = (const __bf16 *)mask;
     hipStream_t st = (hipStream_t)stream;
     const __bf16 *i = (const __bf16 *)in;
     const __bf16 *w = (const __bf16 *)wt;
@@ -865,20 +893,21 @@ int ddf_nn_conv3x3(const void *in, int32_t N, int32_t H, int32_t W, int32_t Cin,
     const bool lds = Cin % 32 == 0 && al16(in) && al16(wt);
 #define DDF_CONV_LDS(PB, NCO)                                                                                      \
     hipLaunchKernelGGL((k_conv3x3_lds<PB, NCO>), dim3((unsigned)(npix / PB), (unsigned)(Cout / (32 * NCO))), dim3(256), \
-                       0, st, i, N, H, W, Cin, in_cs, in_co, w, bias, o, Cout, out_cs, out_co, relu, accumulate)
+                       0, st, i, N, H, W, Cin, in_cs, in_co, w, bias, o, Cout, out_cs, out_co, relu, accumulate, mk,       \
+                       mask_cs, mask_co)
     if (lds && W % 64 == 0 && Cout % 128 == 0) DDF_CONV_LDS(64, 4);
     else if (lds && W % 64 == 0 && Cout % 64 == 0) DDF_CONV_LDS(64, 2);
     else if (lds && W % 32 == 0 && Cout % 128 == 0) DDF_CONV_LDS(32, 4);
     else if (lds && W % 128 == 0) DDF_CONV_LDS(128, 1);
     else if (Cout % 64 == 0 && npix % 64 == 0)
         hipLaunchKernelGGL((k_conv3x3<2, 2>), dim3(npix / 64, Cout / 64), dim3(256), 0, st, i, N, H, W, Cin, in_cs,
-                           in_co, w, bias, o, Cout, out_cs, out_co, relu, accumulate);
+                           in_co, w, bias, o, Cout, out_cs, out_co, relu, accumulate, mk, mask_cs, mask_co);
     else if (npix % 128 == 0)
         hipLaunchKernelGGL((k_conv3x3<4, 1>), dim3(npix / 128, Cout / 32), dim3(256), 0, st, i, N, H, W, Cin, in_cs,
-                           in_co, w, bias, o, Cout, out_cs, out_co, relu, accumulate);
+                           in_co, w, bias, o, Cout, out_cs, out_co, relu, accumulate, mk, mask_cs, mask_co);
     else
         hipLaunchKernelGGL((k_conv3x3<1, 1>), dim3(npix / 32, Cout / 32), dim3(64), 0, st, i, N, H, W, Cin, in_cs,
-                           in_co, w, bias, o, Cout, out_cs, out_co, relu, accumulate);
+                           in_co, w, bias, o, Cout, out_cs, out_co, relu, accumulate, mk, mask_cs, mask_co);
 #undef DDF_CONV_LDS
     return check_launch();
 }
@@ -1027,16 +1056,17 @@ int ddf_nn_pool2(const void *in, int32_t N, int32_t H, int32_t W, int32_t C, voi
     return check_launch();
 }
 
-int ddf_nn_pool2_bwd(const void *dout, int32_t N, int32_t H, int32_t W, int32_t C, void *din, int32_t accumulate,
-                     void *stream)
+int ddf_nn_pool2_bwd(const void *dout, int32_t N, int32_t H, int32_t W, int32_t C, void *din, const void *mask,
+                     int32_t accumulate, void *stream)
 {
     if (H % 2 || W % 2) return fail(DDF_ERR_ARG, "pool2_bwd: H and W must be even");
-    if (C % 8 == 0 && al16(dout) && al16(din))
+    const __bf16 *mk = (const __bf16 *)mask;
+    if (C % 8 == 0 && al16(dout) && al16(din) && (!mask || al16(mask)))
         hipLaunchKernelGGL(k_pool2_bwd8, dim3(blocks_for((int64_t)N * H * W * C / 8)), dim3(256), 0,
-                           (hipStream_t)stream, (const __bf16 *)dout, N, H, W, C, (__bf16 *)din, accumulate);
+                           (hipStream_t)stream, (const __bf16 *)dout, N, H, W, C, (__bf16 *)din, mk, accumulate);
     else
         hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks_for((int64_t)N * H * W * C)), dim3(256), 0, (hipStream_t)stream,
-                           (const __bf16 *)dout, N, H, W, C, (__bf16 *)din, accumulate);
+                           (const __bf16 *)dout, N, H, W, C, (__bf16 *)din, mk, accumulate);
     return check_launch();
 }
 

@@ -202,7 +202,7 @@ class UNet:
         _, _, cip, cop, relu = self._dims(name)
         L.check(L.lib().ddf_nn_conv3x3(_p(src), B, h, w, cip, src_cs, 0, _p(self.wf[name]),
                                        self._wptr(self.w, name, bias=True), _p(dst), cop, cop, 0, int(relu), 0,
-                                       self._s()))
+                                       None, 0, 0, self._s()))
 
     def inputs(self, re, u, H, W):
         """Input tensor for per-sample Reynolds numbers and lid speeds (float32 device tensors)."""
@@ -238,19 +238,21 @@ class UNet:
         return A["head"]
 
     # ---------------------------------------------------------------- backward
-    def _conv_back(self, name, src, src_cs, dsrc, acc, B, h, w):
-        """dY = G[name] (already holds the gradient of the layer output)."""
+    def _conv_back(self, name, src, src_cs, dsrc, acc, B, h, w, src_relu=True):
+        """dY = G[name] holds the gradient of the layer's output, already multiplied by its
+        ReLU's derivative: every producer of a gradient masks its contribution with the
+        activation it flows into (here: the data gradient, masked with `src` when `src` is
+        a ReLU output)."""
         _, _, cip, cop, relu = self._dims(name)
         lib, s = L.lib(), self._s()
-        y, dy = self.A[name], self.G[name]
-        if relu:
-            L.check(lib.ddf_nn_relu_bwd(_p(dy), _p(y), dy.numel(), s))
+        dy = self.G[name]
         L.check(lib.ddf_nn_conv3x3_wgrad(_p(src), B, h, w, cip, src_cs, 0, _p(dy), cop, cop,
                                          self._wptr(self.g, name), self._wptr(self.g, name, bias=True), 0,
                                          _p(self.ws), s))
         if dsrc is not None:
+            mask = _p(src) if src_relu else None
             L.check(lib.ddf_nn_conv3x3(_p(dy), B, h, w, cop, cop, 0, _p(self.wd[name]), None, _p(dsrc), cip, cip, 0, 0,
-                                       int(acc), s))
+                                       int(acc), mask, src_cs, 0, s))
 
     def backward(self, B, H, W):
         """Needs G['head'] = dLoss/dOut; fills self.g with every parameter's gradient."""
@@ -271,10 +273,12 @@ class UNet:
             hh, ww = H >> k, W >> k
             self._conv_back(f"enc{k}b", A[f"enc{k}a"], self.ch[k], G[f"enc{k}a"], 0, B, hh, ww)
             if k > 0:
-                self._conv_back(f"enc{k}a", A[f"pool{k}"], self.ch[k - 1], G[f"pool{k}"], 0, B, hh, ww)
+                # the pooled input is no ReLU output: its gradient is masked per child below
+                self._conv_back(f"enc{k}a", A[f"pool{k}"], self.ch[k - 1], G[f"pool{k}"], 0, B, hh, ww,
+                                src_relu=False)
                 # the pooled input feeds from the previous level's output, which also got a skip gradient
                 L.check(lib.ddf_nn_pool2_bwd(_p(G[f"pool{k}"]), B, 2 * hh, 2 * ww, self.ch[k - 1],
-                                             _p(G[f"enc{k - 1}b"]), 1, s))
+                                             _p(G[f"enc{k - 1}b"]), _p(A[f"enc{k - 1}b"]), 1, s))
             else:
                 self._conv_back("enc0a", self.x, CIN_P, None, 0, B, hh, ww)
 

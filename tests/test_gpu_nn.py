@@ -58,7 +58,7 @@ def test_conv3x3_forward(B, H, W, Cin, Cout, relu):
     b = r.standard_normal(Cout).astype(np.float32)
     bt = torch.tensor(b, device=DEV)
     out = torch.zeros(B * H * W * Cout, dtype=torch.bfloat16, device=DEV)
-    L.check(L.lib().ddf_nn_conv3x3(p(xt), B, H, W, Cin, Cin, 0, p(wft), p(bt), p(out), Cout, Cout, 0, relu, 0, s0()))
+    L.check(L.lib().ddf_nn_conv3x3(p(xt), B, H, W, Cin, Cin, 0, p(wft), p(bt), p(out), Cout, Cout, 0, relu, 0, None, 0, 0, s0()))
     ref = U.conv3x3(x, wq.reshape(9, Cout, Cin), b.astype(np.float64))
     if relu:
         ref = np.maximum(ref, 0)
@@ -72,7 +72,7 @@ def test_conv3x3_slices_and_accumulate():
     big, bigq = bf(r.standard_normal((B, H, W, 64)))
     wt, wq = bf(r.standard_normal((9, Cout, Cin)) / 17)
     out0, out0q = bf(r.standard_normal((B, H, W, 96)))
-    L.check(L.lib().ddf_nn_conv3x3(p(big), B, H, W, Cin, 64, 16, p(wt), None, p(out0), Cout, 96, 32, 0, 1, s0()))
+    L.check(L.lib().ddf_nn_conv3x3(p(big), B, H, W, Cin, 64, 16, p(wt), None, p(out0), Cout, 96, 32, 0, 1, None, 0, 0, s0()))
     ref = out0q.copy()
     ref[..., 32:64] += U.conv3x3(bigq[..., 16:48], wq.reshape(9, Cout, Cin))
     got = np_of(out0, ref.shape)
@@ -92,7 +92,7 @@ def test_conv3x3_data_and_weight_gradients():
     wq = np_of(wf, (9, Cout, Cin))
     dyt, dy = bf(r.standard_normal((B, H, W, Cout)))
     dx = torch.zeros(B * H * W * Cin, dtype=torch.bfloat16, device=DEV)
-    L.check(L.lib().ddf_nn_conv3x3(p(dyt), B, H, W, Cout, Cout, 0, p(wd), None, p(dx), Cin, Cin, 0, 0, 0, s0()))
+    L.check(L.lib().ddf_nn_conv3x3(p(dyt), B, H, W, Cout, Cout, 0, p(wd), None, p(dx), Cin, Cin, 0, 0, 0, None, 0, 0, s0()))
     rdx, rdw, rdb = U.conv3x3_backward(x, wq, dy)
     assert rel(np_of(dx, rdx.shape), rdx) < 1e-2
     ws = torch.empty(L.lib().ddf_nn_wgrad_workspace_bytes(B, H, W, Cin, Cout, None), dtype=torch.uint8, device=DEV)
@@ -119,7 +119,7 @@ def test_pool_up_slice_relu_kernels():
     L.check(L.lib().ddf_nn_up2_bwd(p(gt), B, H // 2, W // 2, C, 24, 8, p(din), s0()))
     assert rel(np_of(din, pq.shape), U.up2_backward(g[..., 8:24])) < 8e-3
     dp = torch.zeros(B * H * W * C, dtype=torch.bfloat16, device=DEV)
-    L.check(L.lib().ddf_nn_pool2_bwd(p(din), B, H, W, C, p(dp), 0, s0()))
+    L.check(L.lib().ddf_nn_pool2_bwd(p(din), B, H, W, C, p(dp), None, 0, s0()))
     assert rel(np_of(dp, x.shape), U.pool2_backward(np_of(din, pq.shape))) < 8e-3
     dst = torch.zeros(B * H * W * 40, dtype=torch.bfloat16, device=DEV)
     L.check(L.lib().ddf_nn_slice(p(xt), C, 0, p(dst), 40, 24, B * H * W, C, 0, s0()))
@@ -153,6 +153,48 @@ def test_cast_weights_multi_matches_per_layer_casts():
             assert torch.all(bufs[3].float() == 3.0)
         wf = bufs[2].float().cpu().numpy().reshape(9, cop, cip)
         assert np.all(wf[:, co:, :] == 0) and np.all(wf[:, :, ci:] == 0)
+
+
+@pytest.mark.parametrize("accumulate", [0, 1])
+@pytest.mark.parametrize("W,Cout", [(64, 32), (128, 32), (64, 64)])   # k_conv3x3<4, 1>; LDS <128, 1>; LDS <64, 2>
+def test_masked_data_gradient_and_pool_adjoint_equal_relu_backward_after(W, Cout, accumulate):
+    # masking each contribution (the fused path of the network's backward) gives the bits
+    # of the unmasked kernel followed by the ReLU adjoint, when what is accumulated into
+    # is already masked
+    r = np.random.default_rng(31 + accumulate + W + Cout)
+    B, H, Cin, cs = 2, 8, 64, 96
+    dyt, _ = bf(r.standard_normal((B, H, W, Cin)))
+    wd, _ = bf(0.1 * r.standard_normal((9, Cout, Cin)))
+    act, _ = bf(r.standard_normal((B, H, W, cs)))              # mask channels [16, 48) of a wider tensor
+    old = torch.where(act[..., 16:16 + Cout] > 0, torch.tensor(r.standard_normal((B, H, W, Cout)), dtype=torch.bfloat16,
+                                                                device=DEV), torch.zeros((), dtype=torch.bfloat16, device=DEV))
+    fused = old.clone().contiguous()
+    ref = old.clone().contiguous()
+    L.check(L.lib().ddf_nn_conv3x3(p(dyt), B, H, W, Cin, Cin, 0, p(wd), None, p(fused), Cout, Cout, 0, 0, accumulate,
+                                   p(act), cs, 16, s0()))
+    L.check(L.lib().ddf_nn_conv3x3(p(dyt), B, H, W, Cin, Cin, 0, p(wd), None, p(ref), Cout, Cout, 0, 0, accumulate,
+                                   None, 0, 0, s0()))
+    mask = act[..., 16:16 + Cout].contiguous()
+    L.check(L.lib().ddf_nn_relu_bwd(p(ref), p(mask), ref.numel(), s0()))
+    torch.cuda.synchronize()
+    assert torch.equal(fused, ref)
+    assert (fused != 0).any()
+    # pooling adjoint, masked per child
+    C = 32
+    d, _ = bf(r.standard_normal((B, H // 2, W // 2, C)))
+    a, _ = bf(r.standard_normal((B, H, W, C)))
+    o = torch.where(a > 0, torch.tensor(r.standard_normal((B, H, W, C)), dtype=torch.bfloat16, device=DEV),
+                    torch.zeros((), dtype=torch.bfloat16, device=DEV))
+    for vec in (True, False):
+        fused = o.clone().contiguous()
+        ref = o.clone().contiguous()
+        Cp = C if vec else C - 3          # C % 8 != 0 takes the single-element kernel
+        L.check(L.lib().ddf_nn_pool2_bwd(p(d), B, H, W, Cp, p(fused), p(a), accumulate, s0()))
+        L.check(L.lib().ddf_nn_pool2_bwd(p(d), B, H, W, Cp, p(ref), None, accumulate, s0()))
+        n = B * H * W * Cp
+        L.check(L.lib().ddf_nn_relu_bwd(p(ref), p(a), n, s0()))
+        torch.cuda.synchronize()
+        assert torch.equal(fused.reshape(-1)[:n], ref.reshape(-1)[:n]), vec
 
 
 def test_mse_and_adam():
@@ -346,7 +388,7 @@ def test_elementwise_kernels_with_unaligned_channel_counts():
     L.check(L.lib().ddf_nn_up2_bwd(p(gt), B, H // 2, W // 2, C, 20, 4, p(din), s0()))
     assert rel(np_of(din, pq.shape), U.up2_backward(g[..., 4:16])) < 8e-3
     dp = torch.zeros(B * H * W * C, dtype=torch.bfloat16, device=DEV)
-    L.check(L.lib().ddf_nn_pool2_bwd(p(din), B, H, W, C, p(dp), 0, s0()))
+    L.check(L.lib().ddf_nn_pool2_bwd(p(din), B, H, W, C, p(dp), None, 0, s0()))
     assert rel(np_of(dp, x.shape), U.pool2_backward(np_of(din, pq.shape))) < 8e-3
     dst, dq = bf(r.standard_normal((B, H, W, 20)))
     L.check(L.lib().ddf_nn_slice(p(xt), C, 0, p(dst), 20, 3, B * H * W, C, 1, s0()))
@@ -374,7 +416,7 @@ def test_conv3x3_lds_configs(B, H, W, Cin, Cout, cs_in, co_in, cs_out, co_out, a
     bt = torch.tensor(b, device=DEV)
     out0, out0q = bf(r.standard_normal((B, H, W, cs_out)))
     L.check(L.lib().ddf_nn_conv3x3(p(xt), B, H, W, Cin, cs_in, co_in, p(wt), p(bt), p(out0), Cout, cs_out, co_out, 1,
-                                   acc, s0()))
+                                   acc, None, 0, 0, s0()))
     ref = np.maximum(U.conv3x3(x[..., co_in:co_in + Cin], wq.reshape(9, Cout, Cin), b.astype(np.float64)), 0)
     if acc:
         ref = ref + out0q[..., co_out:co_out + Cout]
