@@ -898,6 +898,7 @@ int ddf_nn_conv3x3(const void *in, int32_t N, int32_t H, int32_t W, int32_t Cin,
     if (lds && W % 64 == 0 && Cout % 128 == 0) DDF_CONV_LDS(64, 4);
     else if (lds && W % 64 == 0 && Cout % 64 == 0) DDF_CONV_LDS(64, 2);
     else if (lds && W % 32 == 0 && Cout % 128 == 0) DDF_CONV_LDS(32, 4);
+    else if (lds && W % 256 == 0 && Cin == 32 && Cout == 32) DDF_CONV_LDS(256, 1);
     else if (lds && W % 128 == 0) DDF_CONV_LDS(128, 1);
     else if (Cout % 64 == 0 && npix % 64 == 0)
         hipLaunchKernelGGL((k_conv3x3<2, 2>), dim3(npix / 64, Cout / 64), dim3(256), 0, st, i, N, H, W, Cin, in_cs,

@@ -406,7 +406,10 @@ def test_elementwise_kernels_with_unaligned_channel_counts():
     (1, 3, 64, 64, 128, 64, 0, 128, 0, 0),       # 64-pixel segments, 4 channel tiles
     (2, 2, 128, 32, 64, 64, 16, 96, 32, 1),      # 64-pixel segments, 2 tiles, slices, accumulate
     (1, 4, 32, 96, 128, 96, 0, 128, 0, 0),       # 32-pixel segments, 4 tiles
-    (1, 3, 256, 64, 32, 64, 0, 64, 32, 1),       # 128-pixel segments, 1 tile
+    (1, 3, 256, 64, 32, 64, 0, 64, 32, 1),       # 128-pixel segments, 1 tile, slices, accumulate
+    (1, 2, 512, 32, 96, 32, 0, 96, 0, 0),        # 128-pixel segments, 3 channel tiles
+    (2, 3, 256, 32, 32, 64, 16, 64, 32, 1),      # 32 -> 32 channels: 256-pixel segments, slices, accumulate
+    (1, 2, 512, 32, 32, 32, 0, 32, 0, 0),        # 32 -> 32 channels: 256-pixel segments
 ])
 def test_conv3x3_lds_configs(B, H, W, Cin, Cout, cs_in, co_in, cs_out, co_out, acc):
     r = np.random.default_rng(B + H + W + Cin + Cout)
