@@ -202,8 +202,7 @@ def run_batch(steps=20000, count=256):
     b.reduce()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b.step(steps)
-    s = b.reduce()
+    s = b.step_reduce(steps)
     dt = time.perf_counter() - t0
     nodes = b.total_nodes
     return {"instances": count, "nodes": nodes, "mlups": round(nodes * steps / dt / 1e6, 1), "steps": steps,

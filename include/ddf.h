@@ -20,8 +20,8 @@
  *   - All buffers are device memory allocated and owned by the caller; the library
  *     never frees them.  The handle owns host-side state only.
  *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.
- *     Calls are asynchronous on that stream except ddf_reduce and
- *     ddf_batch_reduce, which synchronise it to return host values.
+ *     Calls are asynchronous on that stream except ddf_reduce, ddf_batch_reduce and
+ *     ddf_batch_step_reduce, which synchronise it to return host values.
  *   - Return value: DDF_OK or a negative ddf_status.  No exception or abort crosses
  *     the ABI; ddf_last_error() returns a thread-local message for the last error.
  *   - Lattice units throughout (dx = dt = 1, Sec. 5).  Node (i, j) sits at x = i,
@@ -245,6 +245,13 @@ int ddf_batch_step(ddf_batch *b, int64_t nsteps, void *stream);
  * Returns DDF_ERR_NONFINITE (with out filled) when any instance is non-finite; the
  * other instances' rows stay valid. */
 int ddf_batch_reduce(ddf_batch *b, double *out, void *stream);
+/* ddf_batch_step(b, nsteps) followed by ddf_batch_reduce(b, out): the same state and the
+ * same statistics (bit for bit).  Where the run ends on a whole captured graph (graphs
+ * on, and nsteps minus the one eager step that aligns an odd step count a multiple of
+ * the steps per graph), the last replay carries the reduction kernels, so the K steps
+ * and the reduction are one graph launch and the call only copies the statistics back.
+ * Synchronises the stream. */
+int ddf_batch_step_reduce(ddf_batch *b, int64_t nsteps, double *out, void *stream);
 /* Same as ddf_extract / ddf_get_populations for instance i. */
 int ddf_batch_extract(ddf_batch *b, int32_t i, void *out, uint32_t mask, int32_t out_dtype, void *stream);
 int ddf_batch_get_populations(ddf_batch *b, int32_t i, void *f, void *g, int32_t dtype, void *stream);

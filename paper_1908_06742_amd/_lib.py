@@ -90,6 +90,7 @@ SIGNATURES = {
     "ddf_batch_init_instance": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp]),
     "ddf_batch_step": (C.c_int, [_vp, C.c_int64, _vp]),
     "ddf_batch_reduce": (C.c_int, [_vp, C.POINTER(C.c_double), _vp]),
+    "ddf_batch_step_reduce": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.c_void_p]),
     "ddf_batch_extract": (C.c_int, [_vp, C.c_int32, _vp, C.c_uint32, C.c_int32, _vp]),
     "ddf_batch_get_populations": (C.c_int, [_vp, C.c_int32, _vp, _vp, C.c_int32, _vp]),
 }

@@ -116,6 +116,16 @@ class Batch:
         """Per-instance statistics: dict name -> numpy array of length n."""
         buf = (C.c_double * (self.n * len(L.STATS)))()
         rc = L.lib().ddf_batch_reduce(self._h, buf, _stream_ptr(self.stream))
+        return self._stats(buf, rc, raise_nonfinite)
+
+    def step_reduce(self, nsteps, raise_nonfinite=False):
+        """step(nsteps) then reduce(), with the reduction inside the last graph replay
+        where the run ends on one."""
+        buf = (C.c_double * (self.n * len(L.STATS)))()
+        rc = L.lib().ddf_batch_step_reduce(self._h, int(nsteps), buf, _stream_ptr(self.stream))
+        return self._stats(buf, rc, raise_nonfinite)
+
+    def _stats(self, buf, rc, raise_nonfinite):
         if rc != L.DDF_OK and not (rc == L.DDF_ERR_NONFINITE and not raise_nonfinite):
             L.check(rc)
         a = np.frombuffer(buf, dtype=np.float64).reshape(self.n, len(L.STATS)).copy()

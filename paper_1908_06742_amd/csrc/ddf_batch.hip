@@ -149,6 +149,7 @@ struct ddf_batch {
     // graph
     hipStream_t cap_stream;
     hipGraphExec_t graph_exec;
+    hipGraphExec_t graph_red_exec;   // the same K steps followed by the reduction kernels
     int graph_steps;       // K (even); 0 = eager only
     int captured_steps;    // K of the instantiated graph, 0 = none
 };
@@ -245,6 +246,7 @@ void drop_graph(ddf_batch *b)
 {
     if (b->captured_steps) {
         (void)hipGraphExecDestroy(b->graph_exec);
+        (void)hipGraphExecDestroy(b->graph_red_exec);
         b->captured_steps = 0;
     }
 }
@@ -319,6 +321,31 @@ void launch_one_step(ddf_batch *b, hipStream_t st, int64_t step)
     });
 }
 
+// The reduction kernels of the current state: per-tile FP64 partials (against the
+// residual snapshot when sv, which is then overwritten) and their per-instance sums in
+// d_out.  t is the time index (it matters only for a time-dependent force).
+void launch_reduce(ddf_batch *b, hipStream_t st, bool odd, int sv, int64_t t)
+{
+    with_storage(b->storage, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        using R = typename Codec<S>::R;
+        const auto *inst = (const InstDesc<R> *)b->d_inst;
+        if (odd)
+            hipLaunchKernelGGL((k_batch_reduce<S, true>), dim3(b->ntiles), dim3(kThreads), 0, st, (const S *)b->f,
+                               (const S *)b->g, inst, b->d_tiles, (R *)b->d_snap, sv, t, b->d_partials);
+        else
+            hipLaunchKernelGGL((k_batch_reduce<S, false>), dim3(b->ntiles), dim3(kThreads), 0, st, (const S *)b->f,
+                               (const S *)b->g, inst, b->d_tiles, (R *)b->d_snap, sv, t, b->d_partials);
+        return 0;
+    });
+    hipLaunchKernelGGL(k_reduce_rows<256>, dim3(b->n), dim3(256), 0, st, b->d_partials, b->d_first, b->d_count, 0,
+                       b->d_out);
+}
+
+// Two graphs of K steps from an even step: the plain run, and the run followed by the
+// reduction.  The captured reduction always compares with the snapshot; before the
+// first reduction that comparison reads an unset snapshot, and the host reports no
+// residual for it.  Graphs are used only where the step does not depend on time.
 int capture_graph(ddf_batch *b)
 {
     drop_graph(b);
@@ -329,7 +356,45 @@ int capture_graph(ddf_batch *b)
     hipError_t e = hipGraphInstantiate(&b->graph_exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(DDF_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    DDF_HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < b->graph_steps; ++k) launch_one_step(b, b->cap_stream, k);
+    launch_reduce(b, b->cap_stream, false, 1, b->graph_steps);
+    DDF_HIP_TRY(hipStreamEndCapture(b->cap_stream, &graph));
+    e = hipGraphInstantiate(&b->graph_red_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(b->graph_exec);
+        return fail(DDF_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
     b->captured_steps = b->graph_steps;
+    return DDF_OK;
+}
+
+// Copies the per-instance sums of the last reduction to the host and turns them into
+// the DDF_STAT_* rows of out; the current state becomes the residual snapshot.
+int finish_reduce(ddf_batch *b, double *out, hipStream_t st)
+{
+    std::vector<double> r((size_t)b->n * RS_N);
+    DDF_HIP_TRY(hipMemcpyAsync(r.data(), b->d_out, r.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    DDF_HIP_TRY(hipStreamSynchronize(st));
+    const double K = (double)(b->step - b->snap_step);
+    bool bad = false;
+    for (int i = 0; i < b->n; ++i) {
+        const double *ri = &r[(size_t)i * RS_N];
+        double *o = out + (size_t)i * DDF_NUM_STATS;
+        o[DDF_STAT_MASS] = ri[RS_MASS];
+        o[DDF_STAT_SCALAR] = ri[RS_SCALAR];
+        o[DDF_STAT_RES_U] = (b->snap_valid && K > 0) ? std::sqrt(ri[RS_DU2]) / (K * std::sqrt(ri[RS_U2])) : NAN;
+        o[DDF_STAT_RES_PHI] = (b->snap_valid && K > 0) ? std::sqrt(ri[RS_DPHI2]) / (K * std::sqrt(ri[RS_PHI2])) : NAN;
+        o[DDF_STAT_NONFINITE] = ri[RS_NONFIN];
+        o[DDF_STAT_STEPS] = b->snap_valid ? K : 0.0;
+        o[DDF_STAT_UMAX] = ri[RS_UMAX];
+        o[DDF_STAT_PHIMIN] = ri[RS_PHIMIN];
+        bad |= ri[RS_NONFIN] > 0.0;
+    }
+    b->snap_valid = true;
+    b->snap_step = b->step;
+    if (bad) return fail(DDF_ERR_NONFINITE, "at least one instance holds non-finite values");
     return DDF_OK;
 }
 
@@ -660,43 +725,39 @@ int ddf_batch_reduce(ddf_batch *b, double *out, void *stream)
     if (odd)
         for (int i = 0; i < b->n; ++i)
             if (!b->active[i]) return fail(DDF_ERR_STATE, "reduce at an odd step count while an instance is inactive");
-    const int sv = b->snap_valid ? 1 : 0;
-    with_storage(b->storage, [&](auto *tag) {
-        using S = std::remove_pointer_t<decltype(tag)>;
-        using R = typename Codec<S>::R;
-        const auto *inst = (const InstDesc<R> *)b->d_inst;
-        if (odd)
-            hipLaunchKernelGGL((k_batch_reduce<S, true>), dim3(b->ntiles), dim3(kThreads), 0, st, (const S *)b->f,
-                               (const S *)b->g, inst, b->d_tiles, (R *)b->d_snap, sv, b->step, b->d_partials);
-        else
-            hipLaunchKernelGGL((k_batch_reduce<S, false>), dim3(b->ntiles), dim3(kThreads), 0, st, (const S *)b->f,
-                               (const S *)b->g, inst, b->d_tiles, (R *)b->d_snap, sv, b->step, b->d_partials);
-        return 0;
-    });
-    hipLaunchKernelGGL(k_reduce_rows<256>, dim3(b->n), dim3(256), 0, st, b->d_partials, b->d_first, b->d_count, 0, b->d_out);
+    launch_reduce(b, st, odd, b->snap_valid ? 1 : 0, b->step);
     DDF_HIP_TRY(hipGetLastError());
-    std::vector<double> r((size_t)b->n * RS_N);
-    DDF_HIP_TRY(hipMemcpyAsync(r.data(), b->d_out, r.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    DDF_HIP_TRY(hipStreamSynchronize(st));
-    const double K = (double)(b->step - b->snap_step);
-    bool bad = false;
-    for (int i = 0; i < b->n; ++i) {
-        const double *ri = &r[(size_t)i * RS_N];
-        double *o = out + (size_t)i * DDF_NUM_STATS;
-        o[DDF_STAT_MASS] = ri[RS_MASS];
-        o[DDF_STAT_SCALAR] = ri[RS_SCALAR];
-        o[DDF_STAT_RES_U] = (b->snap_valid && K > 0) ? std::sqrt(ri[RS_DU2]) / (K * std::sqrt(ri[RS_U2])) : NAN;
-        o[DDF_STAT_RES_PHI] = (b->snap_valid && K > 0) ? std::sqrt(ri[RS_DPHI2]) / (K * std::sqrt(ri[RS_PHI2])) : NAN;
-        o[DDF_STAT_NONFINITE] = ri[RS_NONFIN];
-        o[DDF_STAT_STEPS] = b->snap_valid ? K : 0.0;
-        o[DDF_STAT_UMAX] = ri[RS_UMAX];
-        o[DDF_STAT_PHIMIN] = ri[RS_PHIMIN];
-        bad |= ri[RS_NONFIN] > 0.0;
+    return finish_reduce(b, out, st);
+}
+
+int ddf_batch_step_reduce(ddf_batch *b, int64_t nsteps, double *out, void *stream)
+{
+    if (!b) return fail(DDF_ERR_ARG, "batch is NULL");
+    if (!out) return fail(DDF_ERR_ARG, "out is NULL");
+    if (nsteps < 0) return fail(DDF_ERR_ARG, "nsteps < 0");
+    if (!b->initialised) return fail(DDF_ERR_STATE, "step before init");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t K = b->graph_steps, lead = b->step & 1;
+    if (K > 0 && nsteps >= K + lead && (nsteps - lead) % K == 0) {
+        // the run ends on a whole replay: the last one carries the reduction
+        int64_t left = nsteps;
+        if (lead) {
+            launch_one_step(b, st, b->step);
+            b->step++;
+            left--;
+        }
+        if (b->captured_steps != K) {
+            int rc = capture_graph(b);
+            if (rc != DDF_OK) return rc;
+        }
+        for (; left > K; left -= K, b->step += K) DDF_HIP_TRY(hipGraphLaunch(b->graph_exec, st));
+        DDF_HIP_TRY(hipGraphLaunch(b->graph_red_exec, st));
+        b->step += K;
+        return finish_reduce(b, out, st);
     }
-    b->snap_valid = true;
-    b->snap_step = b->step;
-    if (bad) return fail(DDF_ERR_NONFINITE, "at least one instance holds non-finite values");
-    return DDF_OK;
+    int rc = ddf_batch_step(b, nsteps, stream);
+    if (rc != DDF_OK) return rc;
+    return ddf_batch_reduce(b, out, stream);
 }
 
 int ddf_batch_extract(ddf_batch *b, int32_t i, void *out, uint32_t mask, int32_t out_dtype, void *stream)

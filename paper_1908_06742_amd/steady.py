@@ -59,9 +59,8 @@ def batch_run_to_steady(batch, tol=1e-8, max_steps=200_000, check_every=100, fre
     checks = 0
     while steps < max_steps:
         k = min(check_every, max_steps - steps)
-        batch.step(k)
+        s = batch.step_reduce(k)      # the reduction rides in the last graph replay
         steps += k
-        s = batch.reduce()
         checks += 1
         bad |= s["nonfinite"] > 0
         conv = (s["res_u"] < tol) & (s["res_phi"] < tol) & (done_at < 0) & ~bad

@@ -348,8 +348,7 @@ def warm_start_batch(net, batch, re, u, cold_fields, check_steps=100, fallback_t
     batch.init_device(*fields)
     del fields
     batch.reduce(raise_nonfinite=False)
-    batch.step(check_steps)
-    s = batch.reduce(raise_nonfinite=False)
+    s = batch.step_reduce(check_steps, raise_nonfinite=False)
     ru, rp = s["res_u"], s["res_phi"]
     bad = (s["nonfinite"] > 0) | ~np.isfinite(ru) | ~np.isfinite(rp) | (ru > fallback_tol) | (rp > fallback_tol)
     for i in np.nonzero(bad)[0]:

@@ -119,3 +119,10 @@ def test_cast_weights_multi_rejects_bad_tables_before_any_launch():
         arr = (L.CastLayer * 2)(ok, bad)
         assert lib.ddf_nn_cast_weights_multi(2, arr, None) == L.DDF_ERR_ARG
         assert "layer 1" in lib.ddf_last_error().decode()
+
+
+def test_batch_step_reduce_rejects_bad_arguments_before_any_launch():
+    lib = L.lib()
+    buf = (C.c_double * 8)()
+    assert lib.ddf_batch_step_reduce(None, 2, buf, None) == L.DDF_ERR_ARG
+    assert "NULL" in lib.ddf_last_error().decode()

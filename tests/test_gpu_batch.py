@@ -157,6 +157,33 @@ def test_per_instance_statistics_and_nonfinite_flag():
         assert abs(m["scalar"] - s["scalar"][i]) <= 1e-12 * abs(m["scalar"]) + 1e-12, i
 
 
+@pytest.mark.parametrize("graph", [20, 0])
+def test_step_reduce_equals_step_then_reduce(graph):
+    # the reduction inside the last graph replay gives the same state and the same
+    # statistics, bit for bit, as stepping and reducing apart
+    say(f"case: batch step_reduce, {graph} steps per graph")
+    items = mixed_problems("f32")
+    a = Batch([p for p, _ in items], device=DEV)
+    b = Batch([p for p, _ in items], device=DEV)
+    for x in (a, b):
+        x.set_graph(graph)
+        x.init([f for _, f in items])
+    # first reduction (no snapshot yet), whole replays, an odd start aligned by one eager
+    # step, a run with an eager tail, a single replay
+    for n in (40, 40, 1, 41, 30, 20):
+        a.step(n)
+        sa = a.reduce()
+        sb = b.step_reduce(n)
+        assert a.step_count == b.step_count
+        for k in sa:
+            assert np.array_equal(sa[k], sb[k], equal_nan=True), (n, k)
+    assert np.all(np.isfinite(sb["res_u"])) and np.all(sb["steps"] == 20)
+    for i in range(len(items)):
+        fa, ga = a.get_populations(i, raw=True)
+        fb, gb = b.get_populations(i, raw=True)
+        assert torch.equal(fa, fb) and torch.equal(ga, gb), i
+
+
 def test_inactive_instances_hold_state_and_the_rest_match_a_full_batch():
     say("case: batch active mask")
     items = mixed_problems("f32")

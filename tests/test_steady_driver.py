@@ -31,6 +31,9 @@ class ScriptedBatch:
         nf = np.array([1.0 if self.step_count >= self.nonfinite_at.get(i, np.inf) else 0.0 for i in range(self.n)])
         return {"res_u": r.copy(), "res_phi": 0.5 * r, "nonfinite": nf, "mass": np.ones(self.n)}
 
+    def step_reduce(self, k, raise_nonfinite=False):
+        return self.step(k).reduce(raise_nonfinite)
+
     def set_active(self, active):
         if self.step_count % 2:
             raise RuntimeError("odd step count")
