@@ -42,14 +42,15 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x)
     return x;
 }
 
-// Uniform bits for the populations stored at one slot index at one time step: a hash
-// of (slot, step).  The f and g stores at that index take its low and high 16 bits, so
-// distinct (slot, step, lattice) get independent rounding decisions and the same ones
-// the same decisions (runs and checkpoint resumes are reproducible).
+// Uniform bits for one stored population (of each lattice) at one time step: a hash
+// of (key, step), the key naming the node and direction of the stored population.  The
+// f and g stores take its low and high 16 bits, so distinct (node, direction, step,
+// lattice) get independent rounding decisions and the same ones the same decisions
+// (runs and checkpoint resumes are reproducible).
 __device__ __forceinline__ uint32_t sr_step_salt(int64_t t) { return mix32((uint32_t)t + 0x51ed27u); }
-__device__ __forceinline__ uint32_t sr_bits(int64_t slot, uint32_t step_salt)
+__device__ __forceinline__ uint32_t sr_bits(int64_t key, uint32_t step_salt)
 {
-    return mix32(((uint32_t)slot * 0x9e3779b1u) ^ (uint32_t)(slot >> 32) ^ step_salt);
+    return mix32(((uint32_t)key * 0x9e3779b1u) ^ (uint32_t)(key >> 32) ^ step_salt);
 }
 
 template <class S> struct Codec;

@@ -145,10 +145,13 @@ __device__ __forceinline__ void step_node(S *__restrict__ f, S *__restrict__ g, 
     else collide_scalar_mrt(P, M, n, go);
 
     const int64_t cell = (int64_t)y * L.pitch + x;
+    // stochastic-rounding bits (codecs that round to nearest ignore them): keyed by the
+    // step, the node and the direction, which every step writes exactly once each
     const uint32_t salt = sr_step_salt(t);
+    const int64_t key = 9 * cell;
     // rest direction: same slot in both parities
     {
-        const uint32_t h = sr_bits(cell, salt);
+        const uint32_t h = sr_bits(key, salt);
         f[cell] = Codec<S>::enc(fo[0] * P.scale, h);
         g[cell] = Codec<S>::enc(go[0] * P.scale, h >> 16);
     }
@@ -169,7 +172,7 @@ __device__ __forceinline__ void step_node(S *__restrict__ f, S *__restrict__ g, 
         } else {
             slot = (int64_t)a * L.plane + (int64_t)ty * L.pitch + tx;
         }
-        const uint32_t h = sr_bits(slot, salt);
+        const uint32_t h = sr_bits(key + a, salt);
         f[slot] = Codec<S>::enc(vf * P.scale, h);
         g[slot] = Codec<S>::enc(vg * P.scale, h >> 16);
     }
