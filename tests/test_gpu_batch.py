@@ -218,6 +218,17 @@ def test_inactive_instances_hold_state_and_the_rest_match_a_full_batch():
     assert part.step_count == 10 + 47 + 1 + 1 + 1 + 4
 
 
+def test_diverging_instance_is_flagged_while_the_rest_converge():
+    say("case: batch divergence")
+    from paper_1908_06742_amd.steady import batch_run_to_steady
+    probs = [W.cavity_problem(32, 1e5, 0.3, storage="f32"), W.cavity_problem(32, 100.0, 0.1, storage="f32")]
+    b = Batch(probs, device=DEV).init([W.rest_fields(32, 32, 1.0, 0.5)] * 2)
+    r = batch_run_to_steady(b, tol=1e-6, max_steps=20000, check_every=100)
+    assert list(r["status"]) == ["nonfinite", "converged"]
+    out = b.extract(1, ["ux", "phi"])
+    assert all(torch.isfinite(v).all() for v in out.values())
+
+
 def test_init_instance_restarts_one_instance_only():
     say("case: batch init_instance")
     items = mixed_problems("f64")

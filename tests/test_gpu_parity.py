@@ -261,6 +261,18 @@ def test_nonfinite_state_is_reported():
     assert s["nonfinite"] >= 1
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_divergence_near_tau_half_is_reported(storage):
+    # an unresolved cavity (tau = 0.50029) blows up; the reduction reports it as an error
+    say(f"case: divergence, {storage}")
+    pr = W.cavity_problem(32, 1e5, 0.3, storage=storage)
+    lat = Lattice(pr, device=DEV).init(*W.rest_fields(32, 32, 1.0, 0.5)).step(2000)
+    with pytest.raises(DDFError) as e:
+        lat.reduce()
+    assert "NONFINITE" in str(e.value)
+    assert lat.reduce(raise_nonfinite=False)["nonfinite"] > 0
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "bf16sr"])
 def test_checkpoint_resume_is_bit_identical(storage):
     say(f"case: checkpoint {storage}")

@@ -245,3 +245,13 @@ def test_womersley_pulsatile_flow(nthreads):
         # N^phi in this unsteady flow by 2 / (b1 - b2) = 20
         assert oracle.rel_l2(out["wz"][inner, 1], wa[inner]) < 3e-2
         assert oracle.rel_l2(2.0 * out["Sxy"][inner, 1], -wa[inner]) < 2e-3
+
+
+def test_unresolved_cavity_diverges_and_a_resolved_one_does_not():
+    # tau -> 1/2 (Re 1e5 on 32^2 nodes, tau = 0.50029) is unstable: the state goes
+    # non-finite within a few hundred steps; the same cavity at Re 100 stays bounded
+    f0 = W.rest_fields(32, 32, 1.0, 0.5)
+    bad = oracle.Oracle(W.cavity_problem(32, 1e5, 0.3, storage="f64"), nthreads=8).run(f0, 600)[2]
+    good = oracle.Oracle(W.cavity_problem(32, 100.0, 0.3, storage="f64"), nthreads=8).run(f0, 600)[2]
+    assert not np.isfinite(bad["ux"]).all()
+    assert np.isfinite(good["ux"]).all() and np.abs(good["ux"]).max() < 0.5
