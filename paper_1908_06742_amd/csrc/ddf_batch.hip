@@ -74,6 +74,8 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(S *__restrict__ f, S *_
         int x, y;
         if (inst_node(D, tr.tile, x, y))
             step_node<S, SCALAR, true, true, ODD>(f + D.off, g + D.off, D.L, D.P, x, y, t);
+        else if (D.bx_shift >= 6 && pad_slot<S>(D.L, x, y))   // rectangular tiles: x, y were set
+            fill_pad(f + D.off, g + D.off, D.L, x, y);
     }
 }
 
