@@ -358,15 +358,19 @@ int capture_graph(ddf_batch *b)
     hipError_t e = hipGraphInstantiate(&b->graph_exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(DDF_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    DDF_HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < b->graph_steps; ++k) launch_one_step(b, b->cap_stream, k);
-    launch_reduce(b, b->cap_stream, false, 1, b->graph_steps);
-    DDF_HIP_TRY(hipStreamEndCapture(b->cap_stream, &graph));
-    e = hipGraphInstantiate(&b->graph_red_exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) {
+    e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int k = 0; k < b->graph_steps; ++k) launch_one_step(b, b->cap_stream, k);
+        launch_reduce(b, b->cap_stream, false, 1, b->graph_steps);
+        e = hipStreamEndCapture(b->cap_stream, &graph);
+        if (e == hipSuccess) {
+            e = hipGraphInstantiate(&b->graph_red_exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+        }
+    }
+    if (e != hipSuccess) {   // the first graph is not kept without the second
         (void)hipGraphExecDestroy(b->graph_exec);
-        return fail(DDF_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        return fail(DDF_ERR_HIP, std::string("capturing the step-and-reduce graph: ") + hipGetErrorString(e));
     }
     b->captured_steps = b->graph_steps;
     return DDF_OK;
