@@ -83,6 +83,27 @@ def test_batch_fp32_equals_single_lattices():
         assert rel(fa, fb) < 1e-6 and rel(ga, gb) < 1e-6, i
 
 
+@pytest.mark.parametrize("storage", ["f16", "bf16", "bf16sr"])
+def test_batch_low_precision_matches_single_lattices(storage):
+    # 16-bit storage through the batch kernel (its row padding filled per 128-byte line of
+    # 2-byte elements): the stored bits equal the single-lattice kernel's, but for the
+    # rare value whose rounding an FMA contraction of the FP32 arithmetic flips (one ulp,
+    # which spreads to a few neighbours over the steps; with stochastic rounding a changed
+    # value changes later rounding decisions too, so only the size of the differences is
+    # bounded there)
+    say(f"case: batch {storage} vs single lattices")
+    items = mixed_problems(storage)
+    b = Batch([p for p, _ in items], device=DEV)
+    b.init([f for _, f in items]).step(37)
+    for i, (pr, fields) in enumerate(items):
+        lat = Lattice(pr, device=DEV).init(*fields).step(37)
+        if storage != "bf16sr":
+            for x, y in zip(b.get_populations(i, raw=True), lat.get_populations(raw=True)):
+                assert (x != y).float().mean().item() < 2e-2, i
+        for x, y in zip(b.get_populations(i), lat.get_populations()):
+            assert torch.max(torch.abs(x - y)).item() <= 1e-2 * torch.max(torch.abs(y)).item(), i
+
+
 def test_graph_replays_equal_eager_steps():
     say("case: batch graph replay vs eager")
     items = mixed_problems("f32")
