@@ -194,6 +194,35 @@ def test_extraction_inverts_chapman_enskog_relations(seed):
     assert abs(out["Lx"] - (-w * uy)) < 1e-15 and abs(out["Ly"] - w * ux) < 1e-15
 
 
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_invariants_and_lamb_vector_by_matrix_identities(seed):
+    # Sec. 1 defines Q, R and L for the 3D velocity gradient A_ij = d_j u_i.  Checked here
+    # through identities other than the formulas the extraction evaluates: R through the
+    # eigenvalues of S (the omega term vanishes in the plane), Q through -tr(A A) / 2 of the
+    # 3x3 gradient of a divergence-free state, L through a 3D cross product.
+    r = np.random.default_rng(seed)
+    pr = W.taylor_green_problem(4, tau=0.6 + 0.3 * r.random(), tau_phi=0.6 + 0.3 * r.random())
+    rho, ux, uy, phi = 1.0 + 0.05 * r.standard_normal(), 0.05 * r.standard_normal(), 0.05 * r.standard_normal(), 1.0
+    for traceless in (True, False):
+        A = 1e-3 * r.standard_normal((2, 2))
+        if traceless:
+            A[1][1] = -A[0][0]
+        o, f, g = _manufactured(pr, rho, ux, uy, phi, A, np.zeros(2), np.zeros(2))
+        out = o.extract_node(f, g, np.zeros(2))
+        lam = np.linalg.eigvalsh(0.5 * (A + A.T))
+        assert abs(out["R"] - np.sum(lam ** 3) / 3.0) < 1e-15
+        G = np.zeros((3, 3))
+        G[:2, :2] = A
+        Om = 0.5 * (G - G.T)
+        if traceless:
+            assert abs(out["Q"] - (-0.5 * np.trace(G @ G))) < 1e-15
+            assert abs(out["R"]) < 1e-15                        # = -det(G) of a plane flow
+        assert abs(out["Q"] - (-0.5 * np.sum(lam ** 2) + 0.5 * np.sum(Om * Om))) < 1e-15
+        wvec = np.array([G[2][1] - G[1][2], G[0][2] - G[2][0], G[1][0] - G[0][1]])   # curl u
+        L = np.cross(wvec, np.array([ux, uy, 0.0]))
+        assert abs(out["Lx"] - L[0]) < 1e-15 and abs(out["Ly"] - L[1]) < 1e-15 and L[2] == 0.0
+
+
 def test_uniform_flow_has_no_gradient():
     o = oracle.Oracle(W.taylor_green_problem(8))
     f, g = o.init(1.0, 0.03, -0.02, 1.5)
