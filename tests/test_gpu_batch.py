@@ -250,6 +250,36 @@ def test_diverging_instance_is_flagged_while_the_rest_converge():
     assert all(torch.isfinite(v).all() for v in out.values())
 
 
+def test_full_size_batch_sampled_instances_match_oracle():
+    # The 256-instance mix of the benchmark (22.3M nodes, FP32 storage, autotuned tiling)
+    # for one 100-step graph replay carrying the reduction; every instance stays finite and
+    # conserves mass, and sampled instances match the FP64 oracle node for node.
+    say("case: full-size batch, sampled instances")
+    inst = W.batch_instances(256)
+    b = Batch([i.problem for i in inst], device=DEV)
+    b.autotune(steps_per_trial=10)
+    fields = [W.rest_fields(i.nx, i.ny, 1.0, 0.0 if i.kind == "cavity" else 0.5) for i in inst]
+    b.init(fields)
+    s0 = b.reduce()
+    s1 = b.step_reduce(100)
+    assert np.all(s1["nonfinite"] == 0)
+    assert np.all(np.abs(s1["mass"] - s0["mass"]) <= 1e-7 * s0["mass"])
+    nodes = [i.nx * i.ny for i in inst]
+    picks = {int(np.argmin(nodes)), int(np.argmax(nodes)),
+             next(k for k, i in enumerate(inst) if i.kind == "cavity"),
+             next(k for k, i in enumerate(inst) if i.kind == "channel")}
+    for k in sorted(picks):
+        pr = inst[k].problem.with_(storage="f64")
+        _, _, ref = oracle.Oracle(pr, nthreads=8).run(fields[k], 100)
+        out = {n: v.cpu().numpy() for n, v in b.extract(k, ["ux", "uy", "phi"]).items()}
+        # FP32 offset arithmetic against FP64, measured on the instance's own velocity scale
+        u_scale = max(np.max(np.abs(ref["ux"])), np.max(np.abs(ref["uy"])))
+        eu = max(np.max(np.abs(out["ux"] - ref["ux"])), np.max(np.abs(out["uy"] - ref["uy"]))) / u_scale
+        ep = np.max(np.abs(out["phi"] - ref["phi"]))
+        say(f"  instance {k} ({inst[k].kind} {inst[k].nx}x{inst[k].ny}): u {eu:.2e} of max|u| {u_scale:.2e}, phi {ep:.2e}")
+        assert eu < 1e-5 and ep < 1e-5, k
+
+
 def test_init_instance_restarts_one_instance_only():
     say("case: batch init_instance")
     items = mixed_problems("f64")
