@@ -428,3 +428,54 @@ def test_conv3x3_lds_configs(B, H, W, Cin, Cout, cs_in, co_in, cs_out, co_out, a
     untouched = np.ones(cs_out, bool)
     untouched[co_out:co_out + Cout] = False
     assert np.array_equal(got[..., untouched], out0q[..., untouched])
+
+
+@pytest.mark.parametrize("H,Cin,Cout", [
+    (256, 32, 32),     # 32 -> 32 at 256^2: 256-pixel convolution segments, single-tile weight gradient
+    (256, 96, 32),     # the level-0 decoder input: 128-pixel segments
+    (128, 64, 64),     # 64-pixel segments x 2 channel tiles; weight gradient with two output tiles
+    (64, 384, 128),    # the level-2 decoder input: 4 channel tiles
+    (32, 256, 256),    # the bottom level: 32-pixel segments
+])
+def test_full_size_layers_sampled_outputs(H, Cin, Cout):
+    # The surrogate's layer shapes at the training batch (8 x H x H): forward and data
+    # gradient at sampled pixels, computed by the reference on each sample's 3 x 3
+    # neighbourhood (all a centre output depends on), and sampled weight-gradient entries
+    # as plain sums over all pixels.
+    B, W = 8, H
+    r = np.random.default_rng(H + Cin + Cout)
+    xt, x = bf(r.standard_normal((B, H, W, Cin)))
+    dyt, dy = bf(r.standard_normal((B, H, W, Cout)))
+    wmaster = torch.tensor((r.standard_normal((9, Cout, Cin)) / np.sqrt(9 * Cin)).astype(np.float32), device=DEV)
+    wf = torch.empty(9 * Cout * Cin, dtype=torch.bfloat16, device=DEV)
+    wd = torch.empty_like(wf)
+    L.check(L.lib().ddf_nn_cast_weights(p(wmaster), Cout, Cin, Cout, Cin, p(wf), p(wd), s0()))
+    wq = np_of(wf, (9, Cout, Cin))
+    y = torch.empty(B * H * W * Cout, dtype=torch.bfloat16, device=DEV)
+    dx = torch.empty(B * H * W * Cin, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_conv3x3(p(xt), B, H, W, Cin, Cin, 0, p(wf), None, p(y), Cout, Cout, 0, 0, 0, None, 0, 0, s0()))
+    L.check(L.lib().ddf_nn_conv3x3(p(dyt), B, H, W, Cout, Cout, 0, p(wd), None, p(dx), Cin, Cin, 0, 0, 0, None, 0, 0,
+                                   s0()))
+    ws = torch.empty(L.lib().ddf_nn_wgrad_workspace_bytes(B, H, W, Cin, Cout, None), dtype=torch.uint8, device=DEV)
+    dw = torch.empty(9 * Cout * Cin, dtype=torch.float32, device=DEV)
+    db = torch.empty(Cout, dtype=torch.float32, device=DEV)
+    L.check(L.lib().ddf_nn_conv3x3_wgrad(p(xt), B, H, W, Cin, Cin, 0, p(dyt), Cout, Cout, p(dw), p(db), 0, p(ws), s0()))
+    yg, dxg = np_of(y, (B, H, W, Cout)), np_of(dx, (B, H, W, Cin))
+    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (0, 0)))
+    dyp = np.pad(dy, ((0, 0), (1, 1), (1, 1), (0, 0)))
+    pix = [(0, 0, 0), (B - 1, H - 1, W - 1), (1, 0, W - 1)] + \
+          [(int(r.integers(B)), int(r.integers(H)), int(r.integers(W))) for _ in range(40)]
+    got_y, ref_y, got_dx, ref_dx = [], [], [], []
+    for n, i, j in pix:
+        ref_y.append(U.conv3x3(xp[n:n + 1, i:i + 3, j:j + 3, :], wq)[0, 1, 1])
+        got_y.append(yg[n, i, j])
+        ref_dx.append(U.conv3x3_backward(np.zeros((1, 3, 3, Cin)), wq, dyp[n:n + 1, i:i + 3, j:j + 3, :])[0][0, 1, 1])
+        got_dx.append(dxg[n, i, j])
+    assert rel(np.array(got_y), np.array(ref_y)) < 1e-2
+    assert rel(np.array(got_dx), np.array(ref_dx)) < 1e-2
+    dwg, dbg = dw.cpu().numpy().reshape(9, Cout, Cin), db.cpu().numpy()
+    ent = [(int(r.integers(9)), int(r.integers(Cout)), int(r.integers(Cin))) for _ in range(12)]
+    got_w = np.array([dwg[t, co, ci] for t, co, ci in ent])
+    ref_w = np.array([np.sum(dy[..., co] * xp[:, t // 3:t // 3 + H, t % 3:t % 3 + W, ci]) for t, co, ci in ent])
+    assert rel(got_w, ref_w) < 1e-3
+    assert rel(dbg, dy.sum(axis=(0, 1, 2))) < 1e-3
