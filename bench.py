@@ -66,6 +66,7 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=No
     if tile_width:
         lat.set_tile_width(tile_width)
     tile_width = lat.tile_width
+    launch = {"address_width": lat.address_width, "workgroups_per_cu": list(lat.workgroups_per_cu)}
     del fields
     out = torch.empty((16, L, L), dtype=torch.float32, device="cuda")
     names = ["rho", "ux", "uy", "phi", "Sxx", "Syy", "Sxy", "wz"]
@@ -116,6 +117,7 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=No
         "kernel_ms": kern_ms,
         "stats": stats,
         "tile_width": tile_width,
+        "launch": launch,
         "extract_ms": extract_ms,
     }
 
@@ -455,6 +457,7 @@ def main():
             "algorithmic_bytes_per_launch": bpn * nodes,
             "kernel_ms_per_launch": round(r["kernel_ms"], 4),
             "tile_width": r["tile_width"],
+            "launch": r["launch"],
             "copy_gbs": round(cgbs, 1),
             "frac_of_copy": round(achieved / cgbs, 4),
         },
@@ -482,7 +485,7 @@ def main():
                         time_extract=c.get("time_extract", False))
             ach = BYTES_PER_NODE[st] * v["nodes"] / (v["kernel_ms"] * 1e-3) / 1e9
             row = {**c, "size": 8192, "mlups": round(v["mlups"], 1), "kernel_gbs": round(ach, 1),
-                   "frac": round(ach / HBM_PEAK_GBS, 4), "tile_width": v["tile_width"]}
+                   "frac": round(ach / HBM_PEAK_GBS, 4), "tile_width": v["tile_width"], "launch": v["launch"]}
             if v["extract_ms"] is not None:
                 # reads both lattices once (half the step's bytes: 72 B/node in FP32) and
                 # writes 16 FP32 outputs (64 B/node)

@@ -170,6 +170,20 @@ int ddf_set_populations(ddf_handle *h, const void *f, const void *g, int32_t dty
  * The default is 128 for 8- and 4-byte storage and 64 for 2-byte storage. */
 int ddf_set_tile_width(ddf_handle *h, int32_t bx_max);
 int32_t ddf_get_tile_width(const ddf_handle *h);
+/* Width of the lane offsets of the step kernels: 32 (the default where a population
+ * plane is below 4 GiB; DDF_ERR_ARG for a larger plane) or 64 (any size).  With 32 a
+ * plane's base is shared by the wavefront and each address is one 32-bit byte offset,
+ * which holds fewer registers per thread.  Results do not depend on it (bit for bit);
+ * the call drops a captured graph like ddf_set_tile_width. */
+int ddf_set_address_width(ddf_handle *h, int32_t bits);
+int32_t ddf_get_address_width(const ddf_handle *h);
+/* Resident step workgroups per CU for the even and the odd step: 0 (as many as the
+ * registers allow, 4 for most kernels), 2 or 3 (DDF_ERR_ARG otherwise), enforced by
+ * reserving LDS the kernels do not use.  Defaults: lattices whose two population
+ * arrays exceed 256 MB take 2 / 2 in FP32 and 3 / 2 (with 64-bit offsets) in FP16,
+ * others 0 / 0.  Results do not depend on it; the call drops a captured graph. */
+int ddf_set_workgroups_per_cu(ddf_handle *h, int32_t even, int32_t odd);
+int ddf_get_workgroups_per_cu(const ddf_handle *h, int32_t *even, int32_t *odd);
 /* ddf_step replays runs of steps_per_graph steps (even; default 100, 0 = always launch
  * eagerly) captured once into a hipGraph; the remainder and an odd start launch
  * eagerly.  Lattices with a time-dependent force or stochastic rounding always step

@@ -71,6 +71,10 @@ SIGNATURES = {
     "ddf_step_count": (C.c_int64, [_vp]),
     "ddf_set_tile_width": (C.c_int, [_vp, C.c_int32]),
     "ddf_get_tile_width": (C.c_int32, [_vp]),
+    "ddf_set_address_width": (C.c_int, [_vp, C.c_int32]),
+    "ddf_get_address_width": (C.c_int32, [_vp]),
+    "ddf_set_workgroups_per_cu": (C.c_int, [_vp, C.c_int32, C.c_int32]),
+    "ddf_get_workgroups_per_cu": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "ddf_set_graph": (C.c_int, [_vp, C.c_int32]),
     "ddf_last_error": (C.c_char_p, []),
     "ddf_batch_population_bytes": (C.c_size_t, [C.c_int32, _P]),

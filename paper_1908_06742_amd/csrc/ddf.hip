@@ -12,6 +12,8 @@ struct ddf_handle {
     Geom G;
     int tile_width;
     int nblocks;
+    bool idx32;            // step kernels with 32-bit lane offsets (planes below 4 GiB)
+    int wg_cap[2];         // resident step workgroups per CU, even / odd step (0 = no limit)
     int64_t step;
     int64_t snap_step;
     bool snap_valid;
@@ -27,16 +29,39 @@ struct ddf_handle {
 
 namespace {
 
+// Dynamic LDS that limits a 512-thread workgroup of a kernel using no LDS to `cap`
+// resident workgroups per CU (0: no limit).  The CU's LDS size is read once.
+int cap_lds_bytes(int cap)
+{
+    static const int lds_cu = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+            v = 0;
+        return v;
+    }();
+    if (cap <= 0 || lds_cu <= 0) return 0;
+    return (lds_cu / (cap + 1) + 512) / 512 * 512;   // cap of them fit, cap + 1 do not
+}
+
+template <class S, int SC, bool W, bool FO, bool I32>
+void launch_step_kernel(ddf_handle *h, hipStream_t st, bool odd, int64_t t)
+{
+    const auto &P = h->P.of<S>();
+    const int lds = cap_lds_bytes(h->wg_cap[odd ? 1 : 0]);
+    if (odd)
+        hipLaunchKernelGGL((k_step<S, SC, W, FO, true, I32>), dim3(h->nblocks), dim3(kThreads), lds, st, (S *)h->f,
+                           (S *)h->g, h->G, P, t);
+    else
+        hipLaunchKernelGGL((k_step<S, SC, W, FO, false, I32>), dim3(h->nblocks), dim3(kThreads), lds, st, (S *)h->f,
+                           (S *)h->g, h->G, P, t);
+}
+
 template <class S, int SC, bool W, bool FO>
 void launch_step_parity(ddf_handle *h, hipStream_t st, bool odd, int64_t t)
 {
-    const auto &P = h->P.of<S>();
-    if (odd)
-        hipLaunchKernelGGL((k_step<S, SC, W, FO, true>), dim3(h->nblocks), dim3(kThreads), 0, st, (S *)h->f, (S *)h->g,
-                           h->G, P, t);
-    else
-        hipLaunchKernelGGL((k_step<S, SC, W, FO, false>), dim3(h->nblocks), dim3(kThreads), 0, st, (S *)h->f, (S *)h->g,
-                           h->G, P, t);
+    if (h->idx32) launch_step_kernel<S, SC, W, FO, true>(h, st, odd, t);
+    else launch_step_kernel<S, SC, W, FO, false>(h, st, odd, t);
 }
 
 template <class S, int SC>
@@ -128,6 +153,68 @@ int ddf_set_tile_width(ddf_handle *h, int32_t bx_max)
     return DDF_OK;
 }
 
+namespace {
+// Whether every lane offset of the lattice's planes fits 32 bits as a byte count.
+bool plane_fits_32(const ddf_handle *h)
+{
+    return (uint64_t)h->G.L.plane * (uint64_t)storage_size(h->p.storage) < (1ull << 32);
+}
+
+// Launch defaults of the step kernels, measured on the 8192^2 periodic field (one
+// MI355X).  Lattices whose two population arrays exceed the 256 MB Infinity Cache
+// stream from HBM: there fewer resident workgroups per CU made the FP32 steps faster
+// (2 of 4 possible: even step -4.7%, odd -2.4%) and FP16 (3 even, 2 odd, 64-bit
+// offsets); the arithmetic-heavier BF16 codecs and FP64 need every wavefront to hide
+// their latency.  Lattices held by the cache keep every wavefront.
+void launch_defaults(ddf_handle *h)
+{
+    h->idx32 = plane_fits_32(h);
+    h->wg_cap[0] = h->wg_cap[1] = 0;
+    if (2 * population_bytes(&h->p) <= (size_t)256 << 20) return;
+    if (h->p.storage == DDF_F32) {
+        h->wg_cap[0] = h->wg_cap[1] = 2;
+    } else if (h->p.storage == DDF_F16) {
+        h->wg_cap[0] = 3;
+        h->wg_cap[1] = 2;
+        h->idx32 = false;
+    }
+}
+}  // namespace
+
+int ddf_set_address_width(ddf_handle *h, int32_t bits)
+{
+    if (!h) return fail(DDF_ERR_ARG, "handle is NULL");
+    if (bits != 32 && bits != 64) return fail(DDF_ERR_ARG, "address width must be 32 or 64");
+    if (bits == 32 && !plane_fits_32(h))
+        return fail(DDF_ERR_ARG, "a population plane of this lattice is 4 GiB or larger: 64-bit offsets only");
+    if (h->captured_steps) DDF_HIP_TRY(hipDeviceSynchronize());   // a replay may still be running
+    drop_graph(h);
+    h->idx32 = bits == 32;
+    return DDF_OK;
+}
+
+int32_t ddf_get_address_width(const ddf_handle *h) { return !h ? 0 : (h->idx32 ? 32 : 64); }
+
+int ddf_set_workgroups_per_cu(ddf_handle *h, int32_t even, int32_t odd)
+{
+    if (!h) return fail(DDF_ERR_ARG, "handle is NULL");
+    for (int c : {even, odd})
+        if (c != 0 && c != 2 && c != 3) return fail(DDF_ERR_ARG, "workgroups per CU must be 0 (no limit), 2 or 3");
+    if (h->captured_steps) DDF_HIP_TRY(hipDeviceSynchronize());   // a replay may still be running
+    drop_graph(h);
+    h->wg_cap[0] = even;
+    h->wg_cap[1] = odd;
+    return DDF_OK;
+}
+
+int ddf_get_workgroups_per_cu(const ddf_handle *h, int32_t *even, int32_t *odd)
+{
+    if (!h || !even || !odd) return fail(DDF_ERR_ARG, "NULL argument");
+    *even = h->wg_cap[0];
+    *odd = h->wg_cap[1];
+    return DDF_OK;
+}
+
 int ddf_create(const ddf_params *p, void *pop_f, void *pop_g, void *workspace, ddf_handle **out)
 {
     int rc = validate(p);
@@ -145,6 +232,7 @@ int ddf_create(const ddf_params *p, void *pop_f, void *pop_g, void *workspace, d
     h->tile_width = default_tile_width(p->storage);
     h->G = make_geom(*p, h->tile_width);
     h->nblocks = grid_blocks(h->G);
+    launch_defaults(h);
     h->step = 0;
     h->snap_step = 0;
     h->snap_valid = false;

@@ -128,35 +128,64 @@ __device__ __forceinline__ int neighbour(const Lat &L, int x, int y, int dx, int
 // Storage slot holding the logical pre-collision population a of node (x, y) at a
 // step of parity ODD: natural slot after an even number of steps; after an odd number
 // the population sits in the opposite slot of its source node, or (for a population
-// reflected by a wall) in slot a of the node itself.
+// reflected by a wall) in slot a of the node itself.  Returns the cell and sets the
+// plane in *pa.
+template <bool WALLS, bool ODD>
+__device__ __forceinline__ int64_t logical_cell(const Lat &L, int x, int y, int a, int &pa)
+{
+    const int64_t cell = (int64_t)y * L.pitch + x;
+    pa = a;
+    if (!ODD || a == 0) return cell;
+    int sx, sy;
+    const int w = neighbour<WALLS>(L, x, y, -ex(a), -ey(a), sx, sy);
+    if (w >= 0) return cell;
+    pa = opp(a);
+    return (int64_t)sy * L.pitch + sx;
+}
+
 template <bool WALLS, bool ODD>
 __device__ __forceinline__ int64_t logical_slot(const Lat &L, int x, int y, int a)
 {
-    const int64_t cell = (int64_t)y * L.pitch + x;
-    if (!ODD || a == 0) return (int64_t)a * L.plane + cell;
-    int sx, sy;
-    const int w = neighbour<WALLS>(L, x, y, -ex(a), -ey(a), sx, sy);
-    if (w >= 0) return (int64_t)a * L.plane + cell;
-    return (int64_t)opp(a) * L.plane + (int64_t)sy * L.pitch + sx;
+    int pa;
+    const int64_t cell = logical_cell<WALLS, ODD>(L, x, y, a, pa);
+    return (int64_t)pa * L.plane + cell;
 }
 
-template <class S, bool WALLS, bool ODD>
+// Element `cell` of direction plane `pa`.  With IDX32 (planes below 4 GiB) the lane's
+// part of the address is a 32-bit byte offset from the plane's base; where the plane
+// is the same for the whole wavefront (every slot of a periodic lattice) that base
+// stays in scalar registers and the hardware adds the offset in its scalar-base
+// addressing mode, so an address costs one vector register and one 32-bit
+// multiply-add instead of two registers and 64-bit arithmetic.
+template <bool IDX32, class S>
+__device__ __forceinline__ S &elem(S *__restrict__ base, const Lat &L, int pa, int64_t cell)
+{
+    S *p = base + (int64_t)pa * L.plane;
+    if (IDX32) return *(S *)((char *)p + (uint32_t)cell * (uint32_t)sizeof(S));
+    return p[cell];
+}
+
+template <class S, bool WALLS, bool ODD, bool IDX32 = false>
 __device__ __forceinline__ void load_logical(const S *__restrict__ f, const Lat &L, int x, int y,
                                              typename Codec<S>::R inv_scale, typename Codec<S>::R v[9])
 {
 #pragma unroll
-    for (int a = 0; a < 9; ++a) v[a] = Codec<S>::dec(f[logical_slot<WALLS, ODD>(L, x, y, a)]) * inv_scale;
+    for (int a = 0; a < 9; ++a) {
+        int pa;
+        const int64_t c = logical_cell<WALLS, ODD>(L, x, y, a, pa);
+        v[a] = Codec<S>::dec(elem<IDX32>(f, L, pa, c)) * inv_scale;
+    }
 }
 
 // One time step of node (x, y): load both lattices, collide, stream with walls.
-template <class S, int SCALAR, bool WALLS, bool FORCE, bool ODD>
+template <class S, int SCALAR, bool WALLS, bool FORCE, bool ODD, bool IDX32 = false>
 __device__ __forceinline__ void step_node(S *__restrict__ f, S *__restrict__ g, const Lat &L,
                                           const Phys<typename Codec<S>::R> &P, int x, int y, int64_t t)
 {
     using R = typename Codec<S>::R;
     R fv[9], gv[9];
-    load_logical<S, WALLS, ODD>(f, L, x, y, P.inv_scale, fv);
-    load_logical<S, WALLS, ODD>(g, L, x, y, P.inv_scale, gv);
+    load_logical<S, WALLS, ODD, IDX32>(f, L, x, y, P.inv_scale, fv);
+    load_logical<S, WALLS, ODD, IDX32>(g, L, x, y, P.inv_scale, gv);
 
     R m[9], n[9];
     moments(fv, m);
@@ -179,36 +208,35 @@ __device__ __forceinline__ void step_node(S *__restrict__ f, S *__restrict__ g, 
     // rest direction: same slot in both parities
     {
         const uint32_t h = sr_bits(key, salt);
-        f[cell] = Codec<S>::enc(fo[0] * P.scale, h);
-        g[cell] = Codec<S>::enc(go[0] * P.scale, h >> 16);
+        elem<IDX32>(f, L, 0, cell) = Codec<S>::enc(fo[0] * P.scale, h);
+        elem<IDX32>(g, L, 0, cell) = Codec<S>::enc(go[0] * P.scale, h >> 16);
     }
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
         int tx, ty;
         const int w = neighbour<WALLS>(L, x, y, ex(a), ey(a), tx, ty);
         R vf = fo[a], vg = go[a];
-        int64_t slot;
+        int pa = opp(a);
+        int64_t c = cell;
         if (WALLS && w >= 0) {
             // half-way bounce-back (with the moving-wall term) and anti-bounce-back
             // (Dirichlet scalar) land on the node itself, direction opp(a)
             vf = vf - M.rho * P.wall_f[w][a];
             if (P.wall_dirichlet[w]) vg = -vg + P.wall_g[w][a];
-            slot = (int64_t)opp(a) * L.plane + cell;
-        } else if (!ODD) {
-            slot = (int64_t)opp(a) * L.plane + cell;
-        } else {
-            slot = (int64_t)a * L.plane + (int64_t)ty * L.pitch + tx;
+        } else if (ODD) {
+            pa = a;
+            c = (int64_t)ty * L.pitch + tx;
         }
         const uint32_t h = sr_bits(key + a, salt);
-        f[slot] = Codec<S>::enc(vf * P.scale, h);
-        g[slot] = Codec<S>::enc(vg * P.scale, h >> 16);
+        elem<IDX32>(f, L, pa, c) = Codec<S>::enc(vf * P.scale, h);
+        elem<IDX32>(g, L, pa, c) = Codec<S>::enc(vg * P.scale, h >> 16);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-template <class S, int SCALAR, bool WALLS, bool FORCE, bool ODD>
+template <class S, int SCALAR, bool WALLS, bool FORCE, bool ODD, bool IDX32>
 __global__ __launch_bounds__(kThreads) void k_step(S *__restrict__ f, S *__restrict__ g, const Geom G,
                                                    const Phys<typename Codec<S>::R> P, const int64_t t)
 {
@@ -216,7 +244,7 @@ __global__ __launch_bounds__(kThreads) void k_step(S *__restrict__ f, S *__restr
     if (tile >= G.ntiles) return;
     int x, y;
     if (tile_node(tile, G.bx_shift, G.by, G.tiles_x, G.L.nx, G.L.ny, x, y))
-        step_node<S, SCALAR, WALLS, FORCE, ODD>(f, g, G.L, P, x, y, t);
+        step_node<S, SCALAR, WALLS, FORCE, ODD, IDX32>(f, g, G.L, P, x, y, t);
     else if (G.bx_shift >= 6 && pad_slot<S>(G.L, x, y))
         fill_pad(f, g, G.L, x, y);
 }

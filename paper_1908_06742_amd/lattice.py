@@ -83,6 +83,28 @@ class Lattice:
     def tile_width(self):
         return int(L.lib().ddf_get_tile_width(self._h))
 
+    def set_address_width(self, bits):
+        """Lane-offset width of the step kernels (32 where planes are below 4 GiB, or 64);
+        results do not change."""
+        L.check(L.lib().ddf_set_address_width(self._h, int(bits)))
+        return self
+
+    @property
+    def address_width(self):
+        return int(L.lib().ddf_get_address_width(self._h))
+
+    def set_workgroups_per_cu(self, even, odd):
+        """Resident step workgroups per CU for even and odd steps (0 = no limit, 2 or 3);
+        results do not change."""
+        L.check(L.lib().ddf_set_workgroups_per_cu(self._h, int(even), int(odd)))
+        return self
+
+    @property
+    def workgroups_per_cu(self):
+        e, o = C.c_int32(), C.c_int32()
+        L.check(L.lib().ddf_get_workgroups_per_cu(self._h, C.byref(e), C.byref(o)))
+        return int(e.value), int(o.value)
+
     def set_graph(self, steps_per_graph):
         """Steps per captured hipGraph replay (even; 0 = eager launches)."""
         L.check(L.lib().ddf_set_graph(self._h, int(steps_per_graph)))

@@ -80,6 +80,49 @@ def test_valid_create_and_sizes():
         assert rc == 0, msg
 
 
+def test_address_width_follows_the_plane_size():
+    lib = L.lib()
+    for pr, default in ((W.taylor_green_problem(16), 32), (W.Problem(nx=24000, ny=24000, storage="f64"), 64)):
+        p = L.params_from_problem(pr)
+        h = C.c_void_p()
+        assert lib.ddf_create(C.byref(p), C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20), C.byref(h)) == 0
+        try:
+            assert lib.ddf_get_address_width(h) == default
+            assert lib.ddf_set_address_width(h, 64) == 0 and lib.ddf_get_address_width(h) == 64
+            rc = lib.ddf_set_address_width(h, 32)
+            if default == 32:
+                assert rc == 0 and lib.ddf_get_address_width(h) == 32
+            else:
+                assert rc == L.DDF_ERR_ARG and "4 GiB" in lib.ddf_last_error().decode()
+                assert lib.ddf_get_address_width(h) == 64
+            assert lib.ddf_set_address_width(h, 48) == L.DDF_ERR_ARG
+        finally:
+            lib.ddf_destroy(h)
+    assert lib.ddf_set_address_width(None, 32) == L.DDF_ERR_ARG
+
+
+def test_workgroup_caps_default_by_storage_and_size():
+    lib = L.lib()
+    cases = [("f32", 8192, (2, 2), 32), ("f16", 8192, (3, 2), 64), ("bf16", 8192, (0, 0), 32),
+             ("bf16sr", 8192, (0, 0), 32), ("f64", 8192, (0, 0), 32), ("f32", 1024, (0, 0), 32)]
+    for storage, n, caps, bits in cases:
+        p = L.params_from_problem(W.Problem(nx=n, ny=n, storage=storage))
+        h = C.c_void_p()
+        assert lib.ddf_create(C.byref(p), C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20), C.byref(h)) == 0
+        try:
+            e, o = C.c_int32(), C.c_int32()
+            assert lib.ddf_get_workgroups_per_cu(h, C.byref(e), C.byref(o)) == 0
+            assert (e.value, o.value) == caps, storage
+            assert lib.ddf_get_address_width(h) == bits, storage
+            assert lib.ddf_set_workgroups_per_cu(h, 3, 0) == 0
+            assert lib.ddf_get_workgroups_per_cu(h, C.byref(e), C.byref(o)) == 0 and (e.value, o.value) == (3, 0)
+            for bad in ((1, 0), (0, 4), (-1, 2)):
+                assert lib.ddf_set_workgroups_per_cu(h, *bad) == L.DDF_ERR_ARG
+            assert lib.ddf_get_workgroups_per_cu(h, None, C.byref(o)) == L.DDF_ERR_ARG
+        finally:
+            lib.ddf_destroy(h)
+
+
 def test_step_before_init_is_a_state_error():
     p = L.params_from_problem(W.taylor_green_problem(16))
     h = C.c_void_p()

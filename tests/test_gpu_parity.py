@@ -405,6 +405,22 @@ def test_single_lattice_result_independent_of_tile_width(case):
             assert s["mass"] == ref[1]["mass"] and s["scalar"] == ref[1]["scalar"], bx
 
 
+@pytest.mark.parametrize("case, storage", [("cavity_ragged", "f32"), ("fourroll", "f64"), ("fourroll", "bf16sr"),
+                                           ("cavity_ragged", "f16"), ("periodic_wide", "f32"), ("periodic_wide", "bf16")])
+def test_step_result_independent_of_address_width_and_workgroup_caps(case, storage):
+    say(f"case: address widths and workgroup caps {case} {storage}")
+    pr, fields = CASES[case]()
+    pr = pr.with_(storage=storage)
+    out = []
+    for bits, caps in ((32, (0, 0)), (64, (0, 0)), (32, (2, 3)), (64, (3, 2))):
+        lat = Lattice(pr, device=DEV).init(*fields).set_address_width(bits).set_workgroups_per_cu(*caps)
+        assert lat.address_width == bits and lat.workgroups_per_cu == caps
+        lat.step(9)
+        out.append([t.view(torch.uint8) for t in lat.get_populations(raw=True)])
+    for k in range(1, len(out)):
+        assert torch.equal(out[0][0], out[k][0]) and torch.equal(out[0][1], out[k][1]), k
+
+
 def test_graph_capture_refused_where_the_step_depends_on_time():
     pr = W.taylor_green_problem(16, storage="bf16sr")
     lat = Lattice(pr, device=DEV).init(*W.taylor_green_fields(16, 0.01))
