@@ -160,12 +160,14 @@ bool plane_fits_32(const ddf_handle *h)
     return (uint64_t)h->G.L.plane * (uint64_t)storage_size(h->p.storage) < (1ull << 32);
 }
 
-// Launch defaults of the step kernels, measured on the 8192^2 periodic field (one
-// MI355X).  Lattices whose two population arrays exceed the 256 MB Infinity Cache
-// stream from HBM: there fewer resident workgroups per CU made the FP32 steps faster
-// (2 of 4 possible: even step -4.7%, odd -2.4%) and FP16 (3 even, 2 odd, 64-bit
-// offsets); the arithmetic-heavier BF16 codecs and FP64 need every wavefront to hide
-// their latency.  Lattices held by the cache keep every wavefront.
+// Launch defaults of the step kernels, measured on the 8192^2 periodic field and an
+// 8192^2 cavity (one MI355X).  Lattices whose two population arrays exceed the 256 MB
+// Infinity Cache stream from HBM: there fewer resident workgroups per CU made the FP32
+// steps faster (2 of 4 possible; periodic: even step -4.7%, odd -2.4%; cavity -2.4%)
+// and the periodic FP16 step (3 even, 2 odd, 64-bit offsets, -2.3%), while the FP16
+// cavity step, the arithmetic-heavier BF16 codecs and FP64 need every wavefront to
+// hide their latency (the FP16 cavity step was 13% slower with the caps).  Lattices
+// held by the cache keep every wavefront.
 void launch_defaults(ddf_handle *h)
 {
     h->idx32 = plane_fits_32(h);
@@ -173,7 +175,7 @@ void launch_defaults(ddf_handle *h)
     if (2 * population_bytes(&h->p) <= (size_t)256 << 20) return;
     if (h->p.storage == DDF_F32) {
         h->wg_cap[0] = h->wg_cap[1] = 2;
-    } else if (h->p.storage == DDF_F16) {
+    } else if (h->p.storage == DDF_F16 && !has_walls(h->p) && h->p.force_kind == DDF_FORCE_NONE) {
         h->wg_cap[0] = 3;
         h->wg_cap[1] = 2;
         h->idx32 = false;
