@@ -178,11 +178,11 @@ int32_t ddf_get_tile_width(const ddf_handle *h);
 int ddf_set_address_width(ddf_handle *h, int32_t bits);
 int32_t ddf_get_address_width(const ddf_handle *h);
 /* Resident step workgroups per CU for the even and the odd step: 0 (as many as the
- * registers allow, 4 for most kernels), 2 or 3 (DDF_ERR_ARG otherwise), enforced by
+ * registers allow, 4 for most kernels), 1, 2 or 3 (DDF_ERR_ARG otherwise), enforced by
  * reserving LDS the kernels do not use.  Defaults: lattices whose two population
- * arrays exceed 256 MB take 2 / 2 in FP32, and 3 / 2 (with 64-bit offsets) in FP16 when
- * they have neither walls nor a body force; others 0 / 0.  Results do not depend on
- * it; the call drops a captured graph. */
+ * arrays exceed 256 MB take 1 / 1 in FP32 (2 / 2 with walls), and 3 / 2 (with 64-bit
+ * offsets) in FP16 when they have neither walls nor a body force; others 0 / 0.
+ * Results do not depend on it; the call drops a captured graph. */
 int ddf_set_workgroups_per_cu(ddf_handle *h, int32_t even, int32_t odd);
 int ddf_get_workgroups_per_cu(const ddf_handle *h, int32_t *even, int32_t *odd);
 /* ddf_step replays runs of steps_per_graph steps (even; default 100, 0 = always launch

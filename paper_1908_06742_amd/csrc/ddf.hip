@@ -160,21 +160,22 @@ bool plane_fits_32(const ddf_handle *h)
     return (uint64_t)h->G.L.plane * (uint64_t)storage_size(h->p.storage) < (1ull << 32);
 }
 
-// Launch defaults of the step kernels, measured on the 8192^2 periodic field and an
-// 8192^2 cavity (one MI355X).  Lattices whose two population arrays exceed the 256 MB
-// Infinity Cache stream from HBM: there fewer resident workgroups per CU made the FP32
-// steps faster (2 of 4 possible; periodic: even step -4.7%, odd -2.4%; cavity -2.4%)
-// and the periodic FP16 step (3 even, 2 odd, 64-bit offsets, -2.3%), while the FP16
-// cavity step, the arithmetic-heavier BF16 codecs and FP64 need every wavefront to
-// hide their latency (the FP16 cavity step was 13% slower with the caps).  Lattices
-// held by the cache keep every wavefront.
+// Launch defaults of the step kernels, measured on the 8192^2 periodic field (with and
+// without a body force) and an 8192^2 cavity (one MI355X).  Lattices whose two
+// population arrays exceed the 256 MB Infinity Cache stream from HBM: there fewer
+// resident workgroups per CU made the FP32 steps faster (one of the four possible:
+// -6% on the periodic field; two with walls: -2.7% on the cavity, which one made 10%
+// slower) and the periodic FP16 step (3 even, 2 odd, 64-bit offsets, -2.3%), while
+// the FP16 cavity step, the arithmetic-heavier BF16 codecs and FP64 need every
+// wavefront to hide their latency (the FP16 cavity step was 13% slower with caps).
+// Lattices held by the cache keep every wavefront.
 void launch_defaults(ddf_handle *h)
 {
     h->idx32 = plane_fits_32(h);
     h->wg_cap[0] = h->wg_cap[1] = 0;
     if (2 * population_bytes(&h->p) <= (size_t)256 << 20) return;
     if (h->p.storage == DDF_F32) {
-        h->wg_cap[0] = h->wg_cap[1] = 2;
+        h->wg_cap[0] = h->wg_cap[1] = has_walls(h->p) ? 2 : 1;
     } else if (h->p.storage == DDF_F16 && !has_walls(h->p) && h->p.force_kind == DDF_FORCE_NONE) {
         h->wg_cap[0] = 3;
         h->wg_cap[1] = 2;
@@ -201,7 +202,7 @@ int ddf_set_workgroups_per_cu(ddf_handle *h, int32_t even, int32_t odd)
 {
     if (!h) return fail(DDF_ERR_ARG, "handle is NULL");
     for (int c : {even, odd})
-        if (c != 0 && c != 2 && c != 3) return fail(DDF_ERR_ARG, "workgroups per CU must be 0 (no limit), 2 or 3");
+        if (c < 0 || c > 3) return fail(DDF_ERR_ARG, "workgroups per CU must be 0 (no limit), 1, 2 or 3");
     if (h->captured_steps) DDF_HIP_TRY(hipDeviceSynchronize());   // a replay may still be running
     drop_graph(h);
     h->wg_cap[0] = even;

@@ -94,7 +94,7 @@ class Lattice:
         return int(L.lib().ddf_get_address_width(self._h))
 
     def set_workgroups_per_cu(self, even, odd):
-        """Resident step workgroups per CU for even and odd steps (0 = no limit, 2 or 3);
+        """Resident step workgroups per CU for even and odd steps (0 = no limit, 1, 2 or 3);
         results do not change."""
         L.check(L.lib().ddf_set_workgroups_per_cu(self._h, int(even), int(odd)))
         return self
