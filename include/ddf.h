@@ -181,7 +181,8 @@ int32_t ddf_get_address_width(const ddf_handle *h);
  * registers allow, 4 for most kernels), 1, 2 or 3 (DDF_ERR_ARG otherwise), enforced by
  * reserving LDS the kernels do not use.  Defaults: lattices whose two population
  * arrays exceed 256 MB take 1 / 1 in FP32 (2 / 2 with walls), and 3 / 2 (with 64-bit
- * offsets) in FP16 when they have neither walls nor a body force; others 0 / 0.
+ * offsets) in FP16 and BF16 (round to nearest) when they have neither walls nor a body
+ * force; others 0 / 0.
  * Results do not depend on it; the call drops a captured graph. */
 int ddf_set_workgroups_per_cu(ddf_handle *h, int32_t even, int32_t odd);
 int ddf_get_workgroups_per_cu(const ddf_handle *h, int32_t *even, int32_t *odd);

@@ -72,16 +72,11 @@ template <> struct Codec<_Float16> {
 template <> struct Codec<bf16> {
     using R = float;
     __device__ static float dec(bf16 v) { return __uint_as_float(((uint32_t)v.bits) << 16); }
+    // Round to nearest even (NaN stays NaN): the conversion instruction of gfx950.
     __device__ static bf16 enc(float v, uint32_t)
     {
-        uint32_t u = __float_as_uint(v);
         bf16 r;
-        if ((u & 0x7fffffffu) > 0x7f800000u) {          // NaN stays a quiet NaN
-            r.bits = (uint16_t)((u >> 16) | 0x40u);
-        } else {                                        // round to nearest even
-            u += 0x7fffu + ((u >> 16) & 1u);
-            r.bits = (uint16_t)(u >> 16);
-        }
+        r.bits = __builtin_bit_cast(uint16_t, (__bf16)v);
         return r;
     }
 };

@@ -354,6 +354,45 @@ def test_bf16_rounding_of_stored_offsets(storage):
             assert abs(up - frac) < 5 * sigma + 1e-12, (a, frac, up, sigma)
 
 
+def _rne_bf16_bits(x32):
+    """Round-to-nearest-even bfloat16 bit patterns of float32 values (NaN aside)."""
+    u = x32.view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+def test_bf16_encoder_is_round_to_nearest_even_bit_for_bit():
+    # With phi0 = 0 and scale 1 the scalar lattice stores exactly the float32 value of
+    # each population it is given, so the raw plane shows the encoder's bits: ties
+    # (a bfloat16 value plus exactly half an ulp, from even and odd neighbours), values
+    # one bit either side of a tie, float32 subnormals, zeros, infinities and NaN.
+    say("case: bf16 encoder bits")
+    n = 64
+    rng = np.random.default_rng(5)
+    m = 9 * n * n
+    hi = rng.integers(0, 1 << 16, m, dtype=np.uint32)
+    lo = rng.choice(np.array([0x8000, 0x7FFF, 0x8001, 0x0000, 0xFFFF], dtype=np.uint32), m)
+    lo[: m // 2] = rng.integers(0, 1 << 16, m // 2, dtype=np.uint32)
+    bits = (hi << 16) | lo
+    special = np.array([0x00000000, 0x80000000, 0x7F800000, 0xFF800000, 0x00000001, 0x807FFFFF, 0x00408000,
+                        0x00418000, 0x7F7FFFFF, 0x7F7F8000, 0x3F808000, 0x3F818000, 0x7FC00001, 0xFFA00000],
+                       dtype=np.uint32)
+    bits[: special.size] = special
+    x = bits.view(np.float32)
+    pr = W.Problem(nx=n, ny=n, storage="bf16", phi0=0.0)
+    lat = Lattice(pr, device=DEV).init(*W.rest_fields(n, n, 1.0, 0.0))
+    f, _ = lat.get_populations()
+    with np.errstate(invalid="ignore"):              # signalling NaNs among the inputs
+        x64 = x.astype(np.float64)
+    lat.set_populations(f, torch.from_numpy(x64.reshape(9, n, n)))
+    _, g = lat.get_populations(raw=True)
+    got = g.view(torch.int16).cpu().numpy().astype(np.uint16).reshape(-1)
+    nan = np.isnan(x)
+    want = _rne_bf16_bits(x)
+    bad = np.nonzero((got != want) & ~nan)[0]
+    assert bad.size == 0, [(hex(bits[i]), hex(got[i]), hex(want[i])) for i in bad[:8]]
+    assert np.all((got[nan] & 0x7F80) == 0x7F80) and np.all((got[nan] & 0x7F) != 0)
+
+
 def test_bf16sr_runs_are_reproducible_and_differ_from_rne():
     say("case: bf16sr reproducibility")
     pr = W.taylor_green_problem(64, storage="bf16sr")
