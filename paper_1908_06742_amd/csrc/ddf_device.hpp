@@ -86,17 +86,19 @@ template <> struct Codec<bf16> {
 template <> struct Codec<bf16sr> {
     using R = float;
     __device__ static float dec(bf16sr v) { return __uint_as_float(((uint32_t)v.bits) << 16); }
+    // The low 16 bits of `bits` are added below the kept mantissa and the sum is
+    // truncated (infinities stay infinite; NaN stays a quiet NaN).  gfx950's
+    // stochastic-rounding conversion does exactly this with the upper half of its seed
+    // operand, so the seed is bits << 16.
     __device__ static bf16sr enc(float v, uint32_t bits)
     {
-        uint32_t u = __float_as_uint(v);
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
         bf16sr r;
-        if ((u & 0x7fffffffu) > 0x7f800000u) {          // NaN stays a quiet NaN
-            r.bits = (uint16_t)((u >> 16) | 0x40u);
-        } else if ((u & 0x7f800000u) == 0x7f800000u) {  // infinities unchanged
-            r.bits = (uint16_t)(u >> 16);
+        if (v != v) {
+            r.bits = (uint16_t)((__float_as_uint(v) >> 16) | 0x40u);
         } else {
-            u += bits & 0xffffu;
-            r.bits = (uint16_t)(u >> 16);
+            const bf16x2 o = __builtin_amdgcn_cvt_sr_bf16_f32(bf16x2{}, v, bits << 16, false);
+            r.bits = (uint16_t)__builtin_bit_cast(uint32_t, o);
         }
         return r;
     }

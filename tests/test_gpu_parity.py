@@ -393,6 +393,51 @@ def test_bf16_encoder_is_round_to_nearest_even_bit_for_bit():
     assert np.all((got[nan] & 0x7F80) == 0x7F80) and np.all((got[nan] & 0x7F) != 0)
 
 
+def _mix32(x):
+    x = x.astype(np.uint64)
+    m = np.uint64(0xFFFFFFFF)
+    x ^= x >> np.uint64(16)
+    x = (x * np.uint64(0x7FEB352D)) & m
+    x ^= x >> np.uint64(15)
+    x = (x * np.uint64(0x846CA68B)) & m
+    x ^= x >> np.uint64(16)
+    return x
+
+
+def test_bf16sr_encoder_bits_follow_its_definition():
+    # Stochastic rounding adds 16 random bits below the kept bfloat16 mantissa and
+    # truncates.  The bits of a stored slot come from the counter-based hash of (slot,
+    # step salt); a population set at step 0 takes the salt of time index -2 and, in the
+    # scalar lattice, the hash's upper 16 bits.  Checked bit for bit on random float32
+    # patterns (subnormals, values next to the largest finite one, infinities; NaN only
+    # as NaN).
+    say("case: bf16sr encoder bits")
+    n = 64
+    rng = np.random.default_rng(6)
+    m = 9 * n * n
+    bits = rng.integers(0, 1 << 32, m, dtype=np.uint64).astype(np.uint32)
+    special = np.array([0x00000000, 0x80000000, 0x7F800000, 0xFF800000, 0x00000001, 0x807FFFFF, 0x7F7FFFFF,
+                        0xFF7FFFFF, 0x7F7F0001, 0x7FC00001], dtype=np.uint32)
+    bits[: special.size] = special
+    x = bits.view(np.float32)
+    pr = W.Problem(nx=n, ny=n, storage="bf16sr", phi0=0.0)
+    lat = Lattice(pr, device=DEV).init(*W.rest_fields(n, n, 1.0, 0.0))
+    f, _ = lat.get_populations()
+    with np.errstate(invalid="ignore"):              # signalling NaNs among the inputs
+        x64 = x.astype(np.float64)
+    lat.set_populations(f, torch.from_numpy(x64.reshape(9, n, n)))
+    _, g = lat.get_populations(raw=True)
+    got = g.view(torch.int16).cpu().numpy().astype(np.uint16).reshape(-1)
+    slot = np.arange(m, dtype=np.uint64)             # pitch 64 = n, no plane gap: slot = dense index
+    salt = _mix32(np.array([(0xFFFFFFFE + 0x51ED27) & 0xFFFFFFFF], dtype=np.uint64))[0]
+    h = _mix32(((slot * np.uint64(0x9E3779B1)) & np.uint64(0xFFFFFFFF)) ^ salt)
+    want = ((bits.astype(np.uint64) + (h >> np.uint64(16))) >> np.uint64(16)).astype(np.uint16)
+    nan = np.isnan(x)
+    bad = np.nonzero((got != want) & ~nan)[0]
+    assert bad.size == 0, [(hex(bits[i]), hex(got[i]), hex(want[i])) for i in bad[:8]]
+    assert np.all((got[nan] & 0x7F80) == 0x7F80) and np.all((got[nan] & 0x7F) != 0)
+
+
 def test_bf16sr_runs_are_reproducible_and_differ_from_rne():
     say("case: bf16sr reproducibility")
     pr = W.taylor_green_problem(64, storage="bf16sr")
