@@ -180,9 +180,9 @@ int32_t ddf_get_address_width(const ddf_handle *h);
 /* Resident step workgroups per CU for the even and the odd step: 0 (as many as the
  * registers allow, 4 for most kernels), 1, 2 or 3 (DDF_ERR_ARG otherwise), enforced by
  * reserving LDS the kernels do not use.  Defaults: lattices whose two population
- * arrays exceed 256 MB take 1 / 1 in FP32 (2 / 2 with walls), and 3 / 2 (with 64-bit
- * offsets) in FP16 and BF16 (round to nearest) when they have neither walls nor a body
- * force; others 0 / 0.
+ * arrays exceed 256 MB take 1 / 1 in FP64, 1 / 1 in FP32 (2 / 2 with walls), and 3 / 2
+ * (with 64-bit offsets) in FP16 and BF16 (round to nearest) when they have neither walls
+ * nor a body force; others 0 / 0.
  * Results do not depend on it; the call drops a captured graph. */
 int ddf_set_workgroups_per_cu(ddf_handle *h, int32_t even, int32_t odd);
 int ddf_get_workgroups_per_cu(const ddf_handle *h, int32_t *even, int32_t *odd);

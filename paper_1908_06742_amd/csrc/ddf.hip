@@ -165,10 +165,11 @@ bool plane_fits_32(const ddf_handle *h)
 // population arrays exceed the 256 MB Infinity Cache stream from HBM: there fewer
 // resident workgroups per CU made the FP32 steps faster (one of the four possible:
 // -6% on the periodic field; two with walls: -2.7% on the cavity, which one made 10%
-// slower) and the periodic FP16 and BF16 steps (3 even, 2 odd, 64-bit offsets, -2.3%
-// and -2.6%), while the FP16 cavity step, the stochastic-rounding codec and FP64 need
-// every wavefront to hide their latency (the FP16 cavity step was 13% slower with
-// caps).  Lattices held by the cache keep every wavefront.
+// slower), FP64 (one: -4.4% to -5.3% with or without walls and force) and the periodic
+// FP16 and BF16 steps (3 even, 2 odd, 64-bit offsets, -2.3% and -2.6%), while the FP16
+// cavity step and the stochastic-rounding codec need every wavefront to hide their
+// latency (the FP16 cavity step was 13% slower with caps).  Lattices held by the
+// cache keep every wavefront.
 void launch_defaults(ddf_handle *h)
 {
     h->idx32 = plane_fits_32(h);
@@ -176,6 +177,8 @@ void launch_defaults(ddf_handle *h)
     if (2 * population_bytes(&h->p) <= (size_t)256 << 20) return;
     if (h->p.storage == DDF_F32) {
         h->wg_cap[0] = h->wg_cap[1] = has_walls(h->p) ? 2 : 1;
+    } else if (h->p.storage == DDF_F64) {
+        h->wg_cap[0] = h->wg_cap[1] = 1;
     } else if ((h->p.storage == DDF_F16 || h->p.storage == DDF_BF16) && !has_walls(h->p) &&
                h->p.force_kind == DDF_FORCE_NONE) {
         h->wg_cap[0] = 3;
