@@ -53,6 +53,26 @@ def test_create_rejects_invalid_parameters(bad, needle):
     assert rc == L.DDF_ERR_ARG and needle in msg
 
 
+def test_largest_lattice_is_accepted_and_one_row_more_is_not():
+    # 2^31 nodes is the limit; such a lattice takes the 64-bit lane offsets (an FP32
+    # plane of 8 GiB) and its byte counts do not wrap
+    lib = L.lib()
+    for storage, s in (("f32", 4), ("bf16", 2)):
+        pr = W.Problem(nx=65536, ny=32768, storage=storage)
+        p = L.params_from_problem(pr)
+        nb = lib.ddf_population_bytes(C.byref(p))
+        assert nb >= 9 * (1 << 31) * s and nb % 256 == 0
+        h = C.c_void_p()
+        assert lib.ddf_create(C.byref(p), C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20), C.byref(h)) == 0
+        try:
+            assert lib.ddf_get_address_width(h) == 64
+            assert lib.ddf_set_address_width(h, 32) == L.DDF_ERR_ARG
+        finally:
+            lib.ddf_destroy(h)
+        rc, msg = _create(pr.with_(ny=32769))
+        assert rc == L.DDF_ERR_ARG and "2^31" in msg
+
+
 def test_create_rejects_non_power_of_two_scale():
     pr = W.taylor_green_problem(16, storage="f16")
     pr.pop_scale = 3.0

@@ -288,6 +288,54 @@ def test_checkpoint_resume_is_bit_identical(storage):
         assert torch.equal(x.contiguous().view(torch.uint8), y.contiguous().view(torch.uint8))
 
 
+def _wave_fields(xs, ys, xp):
+    """Smooth periodic fields (period 64 in x and y) on the grid xs x ys, for numpy or torch."""
+    X, Y = xp.meshgrid(xs, ys, indexing="xy")
+    t = 2 * math.pi / 64
+    rho = 1.0 + 0.01 * xp.sin(t * X) * xp.cos(t * Y)
+    ux = 0.02 * xp.sin(t * Y + 0.3)
+    uy = 0.02 * xp.cos(t * X - 0.2)
+    phi = 1.0 + 0.1 * xp.sin(t * (X + Y))
+    return rho, ux, uy, phi
+
+
+def test_planes_beyond_4_gib_sampled_nodes():
+    # An FP32 lattice of 32768 x 32832 nodes: each population plane holds 4.3 GB, so the
+    # step takes its 64-bit lane offsets and slots past the first 4 GiB of a plane are
+    # addressed.  The oracle runs a (2k+1)^2 periodic patch around each sample (see the
+    # 8192^2 case), including samples in the last rows.
+    k = 4
+    nx, ny = 32768, 32832
+    say("case: 32768 x 32832 f32 (planes > 4 GiB) sampled nodes")
+    pr = W.Problem(nx=nx, ny=ny, tau=0.8, tau_phi=0.7, storage="f32")
+    xs = torch.arange(nx, dtype=torch.float64, device=DEV)
+    ys = torch.arange(ny, dtype=torch.float64, device=DEV)
+    f = _wave_fields(xs, ys, torch)                  # 4 x 8.6 GB, before the lattice's 90 GB
+    lat = Lattice(pr, device=DEV)
+    assert lat.address_width == 64
+    lat.init(*f)
+    del f
+    torch.cuda.synchronize()
+    lat.step(k)
+    # outputs 0..3 (rho, ux, uy, phi) only: a 4-plane FP32 buffer (17 GB) instead of 16
+    buf = torch.empty((4, ny, nx), dtype=torch.float32, device=DEV)
+    out = lat.extract(["ux", "uy", "phi"], out=buf)
+    samples = [(0, 0), (nx - 1, ny - 1), (nx - 1, ny - 40), (12345, ny - 2), (31000, 30000)]
+    P = 2 * k + 1
+    for sx, sy in samples:
+        o = oracle.Oracle(W.Problem(nx=P, ny=P, tau=pr.tau, tau_phi=pr.tau_phi))
+        wx = (np.arange(P) + sx - k) % nx
+        wy = (np.arange(P) + sy - k) % ny
+        fo, go = o.init(*_wave_fields(wx.astype(np.float64), wy.astype(np.float64), np))
+        o.step(fo, go, k)
+        ref = o.extract(fo, go, k)
+        for name, scale in (("ux", 0.02), ("uy", 0.02), ("phi", 1.0)):
+            got = float(out[name][sy, sx])
+            assert abs(got - ref[name][k, k]) < 1e-5 * scale, (sx, sy, name, got, ref[name][k, k])
+    del out, buf, lat
+    torch.cuda.empty_cache()
+
+
 def test_full_size_vortex_field_sampled_nodes():
     # 8192^2 periodic vortex field, FP32 storage, the benchmark's launch configuration.
     # After k steps a node depends only on nodes within distance k, so the oracle runs a
