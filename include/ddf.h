@@ -167,7 +167,8 @@ int ddf_set_populations(ddf_handle *h, const void *f, const void *g, int32_t dty
 /* Tile shape of every kernel of this lattice: tiles are min(bx_max, row length rounded
  * up to a power of two) nodes wide and 512 / width rows tall, one workgroup each
  * (bx_max = 64, 128, 256 or 512; DDF_ERR_ARG otherwise).  Results do not depend on it.
- * The default is 128 for 8- and 4-byte storage and 64 for 2-byte storage. */
+ * The default is 512 for lattices whose two population arrays fit in 256 MB, else 128
+ * for 8- and 4-byte storage and 64 for 2-byte storage. */
 int ddf_set_tile_width(ddf_handle *h, int32_t bx_max);
 int32_t ddf_get_tile_width(const ddf_handle *h);
 /* Width of the lane offsets of the step kernels: 32 (the default where a population

@@ -138,6 +138,9 @@ def test_workgroup_caps_default_by_storage_and_size():
             assert lib.ddf_get_workgroups_per_cu(h, C.byref(e), C.byref(o)) == 0
             assert (e.value, o.value) == caps, storage
             assert lib.ddf_get_address_width(h) == bits, storage
+            in_cache = 2 * lib.ddf_population_bytes(C.byref(p)) <= 256 << 20
+            want_tw = 512 if in_cache else (64 if storage in ("f16", "bf16", "bf16sr") else 128)
+            assert lib.ddf_get_tile_width(h) == want_tw, (storage, n)
             assert lib.ddf_set_workgroups_per_cu(h, 3, 0) == 0
             assert lib.ddf_get_workgroups_per_cu(h, C.byref(e), C.byref(o)) == 0 and (e.value, o.value) == (3, 0)
             for bad in ((4, 0), (0, 4), (-1, 2)):
