@@ -71,9 +71,10 @@ int ddf_nn_up2_bwd(const void *dout, int32_t N, int32_t h, int32_t w, int32_t C,
 int ddf_nn_slice(const void *src, int32_t s_cs, int32_t s_co, void *dst, int32_t d_cs, int32_t d_co, int64_t npix,
                  int32_t C, int32_t accumulate, void *stream);
 
-/* Weighted MSE of the first 4 channels of out against target (FP32 [npix][4]):
- * *loss_dev = sum_p sum_c w_c (out - t)^2 (FP64, device memory, not averaged);
- * dout = 2 w_c (out - t) / npix (zero in channels >= 4).  weights4: host array. */
+/* Weighted squared error per pixel of the first 4 channels of out against target
+ * (FP32 [npix][4]): *loss_dev = (1/npix) sum_p sum_c w_c (out - t)^2 (FP64, device
+ * memory) and its gradient dout = 2 w_c (out - t) / npix (zero in channels >= 4).
+ * weights4: host array.  workspace: ddf_nn_mse_workspace_bytes(npix) bytes. */
 size_t ddf_nn_mse_workspace_bytes(int64_t npix);
 int ddf_nn_mse(const void *out, int32_t o_cs, const float *target, int64_t npix, const float *weights4, void *dout,
                double *loss_dev, void *workspace, void *stream);

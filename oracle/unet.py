@@ -84,10 +84,11 @@ def up2_backward(dy):
 
 
 def mse(out4, target, weights):
-    """sum_p sum_c w_c (out - t)^2 and its gradient 2 w_c (out - t) / npix."""
+    """Weighted squared error per pixel, loss = (1/npix) sum_p sum_c w_c (out - t)^2, and
+    its gradient with respect to out, 2 w_c (out - t) / npix (one objective for both)."""
     d = out4 - target
     npix = d.shape[0] * d.shape[1] * d.shape[2]
-    loss = float(np.sum(weights * d * d))
+    loss = float(np.sum(weights * d * d)) / npix
     return loss, 2.0 * weights * d / npix
 
 

@@ -697,7 +697,9 @@ __global__ __launch_bounds__(256) void k_mse(const __bf16 *__restrict__ out, int
 
 // out[0] = sum of part[0 .. n): thread t sums part[t], part[t + 256], ... in order, then a
 // fixed-order tree over the 256 thread sums (deterministic).
-__global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ part, int n, double *__restrict__ out)
+// out[0] = (sum of part[0 .. n)) / div, in a fixed order.
+__global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ part, int n, double div,
+                                                 double *__restrict__ out)
 {
     __shared__ double sh[256];
     double s = 0.0;
@@ -708,7 +710,7 @@ __global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ part
         if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = sh[0];
+    if (threadIdx.x == 0) out[0] = sh[0] / div;
 }
 
 // Adam with bias correction on FP32 master weights.
@@ -1119,7 +1121,7 @@ int ddf_nn_mse(const void *out, int32_t o_cs, const float *target, int64_t npix,
     const int vec = o_cs % 8 == 0 && al16(out) && al16(dout);
     hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, (const __bf16 *)out, o_cs, target, npix, weights4[0],
                        weights4[1], weights4[2], weights4[3], (__bf16 *)dout, part, vec);
-    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, st, part, nb, loss_dev);
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, st, part, nb, (double)npix, loss_dev);
     return check_launch();
 }
 

@@ -284,8 +284,8 @@ class UNet:
 
     # ---------------------------------------------------------------- training
     def loss_and_grad(self, target, B, H, W, weights=(1.0, 1.0, 1.0, 1.0)):
-        """MSE of the head output against target (float32 [B*H*W*4]); sets G['head'];
-        returns the device loss (sum over pixels, not averaged)."""
+        """Weighted squared error per pixel of the head output against target (float32
+        [B*H*W*4]); sets G['head'] to its gradient and returns the device loss."""
         wts = (C.c_float * 4)(*weights)
         L.check(L.lib().ddf_nn_mse(_p(self.A["head"]), COUT_P, _p(target), B * H * W, wts, _p(self.G["head"]),
                                    _p(self.loss_dev), _p(self.mse_ws), self._s()))
@@ -373,7 +373,7 @@ def train(net, re, u, targets, H, W, iters, batch_size=8, lr=1e-3, lr_min=1e-5, 
         lr_t = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * it / max(1, iters)))
         loss = net.train_step(re[idx].contiguous(), u[idx].contiguous(), tv[idx].reshape(-1).contiguous(), H, W, lr_t)
         if log is not None and (it % log_every == 0 or it == iters - 1):
-            v = loss.item() / (batch_size * H * W)
+            v = loss.item()
             hist.append((it, v))
             log(it, v, lr_t)
     return hist
@@ -388,8 +388,8 @@ def evaluate_loss(net, re, u, targets, H, W, chunk=16):
         b = min(N, a + chunk)
         net.inputs(re[a:b].contiguous(), u[a:b].contiguous(), H, W)
         net.forward(b - a, H, W)
-        tot += net.loss_and_grad(tv[a:b].reshape(-1).contiguous(), b - a, H, W).item()
-    return tot / (N * H * W)
+        tot += net.loss_and_grad(tv[a:b].reshape(-1).contiguous(), b - a, H, W).item() * (b - a)
+    return tot / N
 
 
 def save_weights(net, path, **meta):

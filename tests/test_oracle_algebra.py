@@ -104,6 +104,27 @@ def test_collision_invariants(model):
             assert abs((fs * EY).sum() - (f * EY).sum() - F[1]) < 1e-15
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_source_moments_have_central_moments_of_a_pure_force(seed):
+    # Sec. 2, the sigma' list: the raw source moments are those of a source whose central
+    # moments about u are (0, F_x, F_y, 0, ..., 0), i.e. it adds momentum F and nothing
+    # else in the frame moving with the fluid.  Mapped to populations with the inverse
+    # pinned by App. B, the central moments are taken here by their definition, so a
+    # wrong, dropped or swapped term in any of the nine entries shows up.
+    r = np.random.default_rng(200 + seed)
+    Fx, Fy = r.standard_normal(2)
+    ux, uy = 0.2 * r.standard_normal(2)
+    _, Tinv, _, _ = oracle.matrices()
+    s = Tinv @ oracle.source_moments(Fx, Fy, ux, uy)
+    cx, cy = EX - ux, EY - uy
+    orders = [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (1, 1), (2, 1), (1, 2), (2, 2)]
+    got = np.array([np.sum(s * cx ** p * cy ** q) for p, q in orders])
+    expect = np.array([0.0, Fx, Fy, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    assert np.max(np.abs(got - expect)) < 1e-15 * max(1.0, abs(Fx), abs(Fy))
+    # and a force-free source is zero
+    assert np.array_equal(oracle.source_moments(0.0, 0.0, ux, uy), np.zeros(9))
+
+
 def test_equilibrium_is_fixed_point():
     o = oracle.Oracle(W.taylor_green_problem(4, omega3=1.4))
     f, g = o.init(1.1, 0.04, -0.03, 1.7)

@@ -140,8 +140,9 @@ def test_poiseuille_vorticity(umax, model, nthreads):
     u = umax * (1.0 - yc * yc / (L * L))
     f, g = o.init(np.ones_like(u), u, 0.0 * u, 1.0 + (y + 0.5) / ny)
     # the parabola and the linear scalar are the steady state up to the wall slip; the
-    # non-equilibrium moments settle within a few relaxation times
-    steps = 3000
+    # remaining transient decays on the viscous and diffusive time scales of the channel
+    # (d_y phi is off by 1.4e-7 after 3000 steps, 1.3e-8 after 10k and 2e-9 after 30k)
+    steps = 30000
     o.step(f, g, steps)
     out = o.extract(f, g, steps)
     wz = 2.0 * umax * yc / (L * L)
@@ -156,7 +157,7 @@ def test_poiseuille_vorticity(umax, model, nthreads):
     assert np.max(np.abs(out["Sxx"][inner])) < 2e-3 * np.max(np.abs(wz))
     # scalar: linear profile between the half-way Dirichlet walls, exact gradient
     assert np.max(np.abs(out["phi"] - (1.0 + (y + 0.5) / ny))) < 1e-6
-    assert np.max(np.abs(out["dyphi"] * ny - 1.0)) < 1e-3
+    assert np.max(np.abs(out["dyphi"] - 1.0 / ny)) < 1e-8
 
 
 def test_couette_vorticity_and_moving_wall(nthreads):

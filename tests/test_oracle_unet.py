@@ -68,14 +68,28 @@ def test_backward_matches_finite_differences():
 
 
 def test_mse_gradient():
+    # the returned gradient is that of the returned loss: central differences of the
+    # loss (a quadratic, so they are exact up to rounding) at every element
     r = np.random.default_rng(4)
     o = r.standard_normal((2, 4, 4, 4))
     t = r.standard_normal((2, 4, 4, 4))
     w = np.array([1.0, 0.5, 2.0, 1.5])
     loss, d = U.mse(o, t, w)
-    assert np.isclose(loss, np.sum(w * (o - t) ** 2))
-    npix = 32
-    assert np.allclose(d, 2 * w * (o - t) / npix)
+    # the loss is the per-pixel mean of the weighted squared error (a plain loop)
+    ref = 0.0
+    for n in range(2):
+        for i in range(4):
+            for j in range(4):
+                ref += sum(w[c] * (o[n, i, j, c] - t[n, i, j, c]) ** 2 for c in range(4))
+    assert abs(loss - ref / 32.0) < 1e-14
+    eps = 1e-4
+    fd = np.empty_like(o)
+    for idx in np.ndindex(o.shape):
+        op, om = o.copy(), o.copy()
+        op[idx] += eps
+        om[idx] -= eps
+        fd[idx] = (U.mse(op, t, w)[0] - U.mse(om, t, w)[0]) / (2.0 * eps)
+    assert np.max(np.abs(fd - d)) < 1e-10
 
 
 def test_bf16_round_matches_torch_conversion():
