@@ -237,6 +237,7 @@ def run_surrogate(count=16, cap=400_000):
     net, _ = S.load_weights(os.path.join(ROOT, "paper_1908_06742_amd", "weights", "unet_cavity256.npz"))
     S.predict_batch_fields(net, re, u, n, n)       # first call allocates the activations
     b = Batch(probs, device="cuda")
+    b.autotune(10)                                  # cached: applies the probe's tiling
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     z = torch.zeros((count, n, n), dtype=torch.float64, device="cuda")
@@ -246,6 +247,7 @@ def run_surrogate(count=16, cap=400_000):
     t_cold = time.perf_counter() - t0
     del b
     b = Batch(probs, device="cuda")
+    b.autotune(10)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fb = S.warm_start_batch(net, b, re, u, lambda i: W.cavity_fields(n))

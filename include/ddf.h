@@ -144,7 +144,17 @@ void ddf_destroy(ddf_handle *h);
 int ddf_init_equilibrium(ddf_handle *h, const double *rho, const double *ux, const double *uy,
                          const double *phi, void *stream);
 
-/* Advance nsteps >= 0 time steps (collide both lattices, stream with walls). */
+/* Advance nsteps >= 0 time steps.  Per step and node: the fluid populations are
+ * collided in raw-moment space with the trapezoidal body-force source (Sec. 2,
+ * eq. MRT-LBEfluidmotion_transformed with eqs. eqmrawmoment, relaxationtimematrix_fluidmotion
+ * and the sigma' source list), the scalar populations with the anisotropic MRT
+ * collision (Sec. 3, eq. MRT-LBECDE with eqs. eqmrawmoment_CDE, relaxationtimematrix_CDE),
+ * or the SRT (App. B) or central-moment (App. C, App. D) variant selected by
+ * scalar_model; both lattices are then streamed in place (the AA pattern: even steps
+ * write a node's post-collision populations into its own opposite slots, odd steps into
+ * the neighbours' natural slots), with half-way walls, moving walls and Dirichlet scalar
+ * walls applied as the populations are written.  Asynchronous on `stream`;
+ * DDF_ERR_STATE before ddf_init_equilibrium or ddf_set_populations. */
 int ddf_step(ddf_handle *h, int64_t nsteps, void *stream);
 
 /* Local kinematics of the current state (pre-collision populations at the current

@@ -10,7 +10,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from .lattice import _TORCH_STORAGE, _ptr, _stream_ptr
+from .lattice import _TORCH_STORAGE, _ptr, _stream_ptr, check_field, out_dtype_code, output_mask
 
 
 class Batch:
@@ -65,7 +65,8 @@ class Batch:
 
     def init_device(self, rho, ux, uy, phi):
         """Initialise from concatenated FP64 device tensors (instance order, [ny][nx] each)."""
-        fields = [t.to(self.device, torch.float64).contiguous().reshape(-1) for t in (rho, ux, uy, phi)]
+        fields = [check_field(t.to(self.device, torch.float64).contiguous().reshape(-1), self.total_nodes, nm)
+                  for t, nm in zip((rho, ux, uy, phi), ("rho", "ux", "uy", "phi"))]
         L.check(L.lib().ddf_batch_init_equilibrium(self._h, *[_ptr(t) for t in fields], _stream_ptr(self.stream)))
         self._keep = fields
         return self
@@ -73,12 +74,12 @@ class Batch:
     def init_instance(self, i, rho, ux, uy, phi):
         p = self.problems[i]
 
-        def dev(a):
+        def dev(a, nm):
             if not torch.is_tensor(a):
                 a = torch.as_tensor(np.array(np.broadcast_to(np.asarray(a, np.float64), (p.ny, p.nx))))
-            return a.to(self.device, torch.float64).contiguous()
+            return check_field(a.to(self.device, torch.float64).contiguous(), p.ny * p.nx, nm)
 
-        fields = [dev(a) for a in (rho, ux, uy, phi)]
+        fields = [dev(a, nm) for a, nm in zip((rho, ux, uy, phi), ("rho", "ux", "uy", "phi"))]
         L.check(L.lib().ddf_batch_init_instance(self._h, int(i), *[_ptr(t) for t in fields], _stream_ptr(self.stream)))
         self._keep_i = fields
         return self
@@ -134,12 +135,10 @@ class Batch:
     def extract(self, i, names=None, dtype=torch.float64):
         p = self.problems[i]
         names = list(L.OUTPUTS) if names is None else list(names)
-        mask = 0
-        for nm in names:
-            mask |= 1 << L.OUTPUTS.index(nm)
+        mask = output_mask(names)
+        od = out_dtype_code(dtype)
         out = torch.empty((len(L.OUTPUTS), p.ny, p.nx), dtype=dtype, device=self.device)
-        L.check(L.lib().ddf_batch_extract(self._h, int(i), _ptr(out), mask, 0 if dtype == torch.float64 else 1,
-                                          _stream_ptr(self.stream)))
+        L.check(L.lib().ddf_batch_extract(self._h, int(i), _ptr(out), mask, od, _stream_ptr(self.stream)))
         return {nm: out[L.OUTPUTS.index(nm)] for nm in names}
 
     def get_populations(self, i, raw=False):

@@ -12,9 +12,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <mutex>
 #include <new>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -98,10 +100,15 @@ __global__ __launch_bounds__(kThreads) void k_batch_reduce(const S *__restrict__
     block_reduce_stats<kThreads>(sh, v, partials + (int64_t)blockIdx.x * RS_N);
 }
 
+// A tuning result applies to batches with the same storage, scalar collision model and
+// instances of the same sizes and boundary kinds (periodic x, periodic y, body force).
 struct TuneKey {
-    int storage;
-    std::vector<std::pair<int, int>> sizes;
-    bool operator<(const TuneKey &o) const { return storage != o.storage ? storage < o.storage : sizes < o.sizes; }
+    int storage, scalar_model;
+    std::vector<std::array<int, 5>> inst;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(storage, scalar_model, inst) < std::tie(o.storage, o.scalar_model, o.inst);
+    }
 };
 
 std::map<TuneKey, std::pair<int, int>> &tune_cache()
@@ -650,9 +657,15 @@ int ddf_batch_autotune(ddf_batch *b, int32_t steps_per_trial, int32_t *bx_max_ou
     if (!b) return fail(DDF_ERR_ARG, "batch is NULL");
     if (steps_per_trial < 2) return fail(DDF_ERR_ARG, "steps_per_trial must be >= 2");
     hipStream_t st = (hipStream_t)stream;
+    // the tile lists are replaced below, which a replay of a captured graph may still read
+    int qrc = quiesce();
+    if (qrc != DDF_OK) return qrc;
     TuneKey key;
     key.storage = b->storage;
-    for (int i = 0; i < b->n; ++i) key.sizes.push_back({b->p[i].nx, b->p[i].ny});
+    key.scalar_model = b->scalar_model == DDF_SCALAR_CASCADED ? DDF_SCALAR_CENTRAL : b->scalar_model;
+    for (int i = 0; i < b->n; ++i)
+        key.inst.push_back({b->p[i].nx, b->p[i].ny, b->p[i].periodic_x ? 1 : 0, b->p[i].periodic_y ? 1 : 0,
+                            b->p[i].force_kind});
     {
         std::lock_guard<std::mutex> lk(tune_mutex());
         auto it = tune_cache().find(key);

@@ -25,6 +25,67 @@ def _ptr(t: torch.Tensor):
     return C.c_void_p(t.data_ptr())
 
 
+_OUT_DTYPES = {torch.float64: 0, torch.float32: 1}
+
+
+def _same_device(a: torch.device, b: torch.device) -> bool:
+    if a.type != b.type:
+        return False
+    if a.type != "cuda" or a.index == b.index:
+        return True
+    cur = torch.cuda.current_device()
+    return (a.index if a.index is not None else cur) == (b.index if b.index is not None else cur)
+
+
+def out_dtype_code(dtype) -> int:
+    """Output type code of the extraction calls (0 = float64, 1 = float32)."""
+    if dtype not in _OUT_DTYPES:
+        raise ValueError(f"extraction writes float64 or float32 planes, not {dtype}")
+    return _OUT_DTYPES[dtype]
+
+
+def output_mask(names) -> int:
+    mask = 0
+    for n in names:
+        if n not in L.OUTPUTS:
+            raise ValueError(f"unknown output {n!r}; choose from {L.OUTPUTS}")
+        mask |= 1 << L.OUTPUTS.index(n)
+    return mask
+
+
+def check_extract_out(out, mask, ny, nx, device) -> int:
+    """The extraction kernels write plane k of `out` (k * ny * nx elements in) for every
+    bit k of mask: `out` must be a contiguous float32/float64 tensor on the lattice's
+    device holding at least (highest bit + 1) planes.  Returns the dtype code."""
+    if not torch.is_tensor(out):
+        raise ValueError("out must be a torch tensor")
+    code = out_dtype_code(out.dtype)
+    if not _same_device(out.device, device):
+        raise ValueError(f"out is on {out.device}, the lattice on {device}")
+    if not out.is_contiguous():
+        raise ValueError("out must be contiguous")
+    need = mask.bit_length() * ny * nx
+    if out.numel() < need:
+        raise ValueError(f"out holds {out.numel()} elements; the selected outputs need {need} "
+                         f"({mask.bit_length()} planes of {ny} x {nx})")
+    return code
+
+
+def check_field(t, n, what):
+    """A dense field handed to the kernels, which read exactly n float64 elements."""
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{what}: need a contiguous float64 tensor of {n} elements, got "
+                         f"{tuple(t.shape)} {t.dtype}{'' if t.is_contiguous() else ' (not contiguous)'}")
+    return t
+
+
+def check_populations(t, ny, nx, what):
+    """Logical populations, direction-major (9, ny, nx)."""
+    if tuple(t.shape) != (9, ny, nx):
+        raise ValueError(f"{what}: need shape (9, {ny}, {nx}), got {tuple(t.shape)}")
+    return t
+
+
 class Lattice:
     """A fluid lattice f and a scalar lattice g (caller-owned torch buffers).
 
@@ -65,8 +126,11 @@ class Lattice:
     # -- state -----------------------------------------------------------------
     def _field(self, a):
         t = torch.as_tensor(a, dtype=torch.float64)
-        t = torch.broadcast_to(t, (self.ny, self.nx)).to(self.device).contiguous()
-        return t
+        try:
+            t = torch.broadcast_to(t, (self.ny, self.nx))
+        except RuntimeError as e:
+            raise ValueError(f"field of shape {tuple(t.shape)} does not broadcast to ({self.ny}, {self.nx})") from e
+        return check_field(t.to(self.device).contiguous(), self.ny * self.nx, "field")
 
     def init(self, rho, ux, uy, phi):
         fields = [self._field(a) for a in (rho, ux, uy, phi)]
@@ -121,14 +185,15 @@ class Lattice:
     def extract(self, names=None, dtype=torch.float64, out=None):
         """Local kinematics of the current state: dict name -> (ny, nx) tensor."""
         names = list(L.OUTPUTS) if names is None else list(names)
-        mask = 0
-        for n in names:
-            mask |= 1 << L.OUTPUTS.index(n)
+        mask = output_mask(names)
         if out is None:
+            out_dtype_code(dtype)
             out = torch.empty((len(L.OUTPUTS), self.ny, self.nx), dtype=dtype, device=self.device)
-        od = 0 if out.dtype == torch.float64 else 1
+        od = check_extract_out(out, mask, self.ny, self.nx, self.device)
         L.check(L.lib().ddf_extract(self._h, _ptr(out), mask, od, _stream_ptr(self.stream)))
-        return {n: out[L.OUTPUTS.index(n)] for n in names}
+        flat, plane = out.view(-1), self.ny * self.nx
+        return {n: flat[L.OUTPUTS.index(n) * plane:(L.OUTPUTS.index(n) + 1) * plane].view(self.ny, self.nx)
+                for n in names}
 
     def reduce(self, raise_nonfinite=True):
         buf = (C.c_double * len(L.STATS))()
@@ -149,8 +214,8 @@ class Lattice:
 
     def set_populations(self, f, g, step=0, raw=False):
         dt = _TORCH_STORAGE[self.params.storage] if raw else torch.float64
-        f = torch.as_tensor(f).to(self.device, dt).contiguous()
-        g = torch.as_tensor(g).to(self.device, dt).contiguous()
+        f = check_populations(torch.as_tensor(f), self.ny, self.nx, "f").to(self.device, dt).contiguous()
+        g = check_populations(torch.as_tensor(g), self.ny, self.nx, "g").to(self.device, dt).contiguous()
         L.check(L.lib().ddf_set_populations(self._h, _ptr(f), _ptr(g), 1 if raw else 0, int(step),
                                             _stream_ptr(self.stream)))
         self._keep = (f, g)
