@@ -26,7 +26,8 @@ LB_STEPS_PER_STEP = 100
 BYTES_PER_NODE = {"f64": 288, "f32": 144, "f16": 72, "bf16": 72, "bf16sr": 72}
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_vortex8192_f32_counters.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1908_06742_amd", "csrc", n)
-                  for n in ("ddf.hip", "ddf_kernels.hpp", "ddf_device.hpp")]
+                  for n in ("ddf.hip", "ddf_kernels.hpp", "ddf_device.hpp", "ddf_handle.hpp", "ddf_step_launch.hpp",
+                            "ddf_step_row.hip", "ddf_step_il.hip")]
 
 
 def kernel_hash():
@@ -48,8 +49,34 @@ def measured_traffic(nodes, tile_width):
     return d.get("bytes_per_launch")
 
 
+def time_parities(lat, stream, pairs=20):
+    """Mean duration of one even and one odd step launch (HIP events around each eager
+    launch on the lattice's stream), then the graph replays are restored."""
+    import torch
+
+    graphs = lat.problem.force_kind != "pulsatile" and lat.problem.storage != "bf16sr"
+    if graphs:
+        lat.set_graph(0)
+    if lat.step_count % 2:
+        lat.step(1)
+    lat.step(2)
+    torch.cuda.synchronize()
+    ev = {0: [], 1: []}
+    for _ in range(2 * pairs):
+        par = lat.step_count % 2
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lat.step(1)
+        e1.record(stream)
+        ev[par].append((e0, e1))
+    torch.cuda.synchronize()
+    if graphs:
+        lat.set_graph(LB_STEPS_PER_STEP)
+    return {p: sum(a.elapsed_time(b) for a, b in v) / len(v) for p, v in ev.items()}
+
+
 def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=None, scalar_model="mrt",
-            pulsatile=False, time_extract=False):
+            pulsatile=False, time_extract=False, parity_steps=False):
     import numpy as np
     import torch
 
@@ -66,7 +93,8 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=No
     if tile_width:
         lat.set_tile_width(tile_width)
     tile_width = lat.tile_width
-    launch = {"address_width": lat.address_width, "workgroups_per_cu": list(lat.workgroups_per_cu)}
+    launch = {"layout": lat.layout, "address_width": lat.address_width,
+              "workgroups_per_cu": list(lat.workgroups_per_cu)}
     del fields
     out = torch.empty((16, L, L), dtype=torch.float32, device="cuda")
     names = ["rho", "ux", "uy", "phi", "Sxx", "Syy", "Sxy", "wz"]
@@ -98,6 +126,7 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=No
     dt = time.perf_counter() - t0
     kern_ms = sum(a.elapsed_time(b) for a, b in evs) / (steps * lb_steps)
     stats = dict(last)
+    parity_ms = time_parities(lat, stream) if parity_steps else None
     extract_ms = None
     if time_extract:
         # all 16 outputs (rho, u, phi, S, omega, gradients, Q, R, Lamb vector) in FP32
@@ -119,6 +148,7 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=No
         "tile_width": tile_width,
         "launch": launch,
         "extract_ms": extract_ms,
+        "parity_ms": parity_ms,
     }
 
 
@@ -167,23 +197,51 @@ def run_cavity(n=1024, cap=200_000, tol=1e-8):
             "omega_vs_fd_curl_rel_l2": ew, "omega_vs_fd_curl_rel_l2_centre_quarter": ec}
 
 
-def copy_gbs(nbytes=1 << 30, reps=5):
-    """Best of `reps` device-to-device copies of nbytes (read + write bytes per second)."""
+def stream_ceilings(nbytes=2 << 30, reps=5):
+    """What plain streams reach on this device, from the library's reference kernels
+    (ddf_bandwidth_probe): the best copy (read + write bytes per second), read-only
+    and write-only pass over `nbytes` (8x the 256 MB Infinity Cache) across their
+    launch variants, plus torch's own device-to-device copy for comparison."""
+    import ctypes as C
+
     import torch
 
+    from paper_1908_06742_amd import _lib as L
+
+    lib = L.lib()
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    best = 1e30
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        dst.copy_(src)
-        e1.record()
-        e1.synchronize()
-        best = min(best, e0.elapsed_time(e1))
+    stream = torch.cuda.current_stream()
+    sp = C.c_void_p(stream.cuda_stream)
+
+    def best_ms(fn):
+        fn()
+        best = 1e30
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    out = {"bytes": nbytes}
+    for kind, name, factor in ((L.PROBE_COPY, "copy", 2.0), (L.PROBE_READ, "read", 1.0), (L.PROBE_WRITE, "write", 1.0)):
+        rows = []
+        for unroll in (1, 2, 4, 8):
+            for nt in (0, 1):
+                def fn():
+                    L.check(lib.ddf_bandwidth_probe(kind, unroll, nt, C.c_void_p(src.data_ptr()),
+                                                    C.c_void_p(dst.data_ptr()), nbytes, sp))
+                ms = best_ms(fn)
+                rows.append((factor * nbytes / (ms * 1e-3) / 1e9, unroll, nt))
+        gbs, unroll, nt = max(rows)
+        out[f"{name}_gbs"] = round(gbs, 1)
+        out[f"{name}_variant"] = {"unroll": unroll, "nontemporal": nt}
+    out["torch_copy_gbs"] = round(2.0 * nbytes / (best_ms(lambda: dst.copy_(src)) * 1e-3) / 1e9, 1)
     del src, dst
-    return 2.0 * nbytes / (best * 1e-3) / 1e9
+    return out
 
 
 def run_batch(steps=20000, count=256):
@@ -390,8 +448,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 1024^2 cavity, 256-instance batch and surrogate time-to-steady lines")
     ap.add_argument("--batch-steps", type=int, default=20000)
-    ap.add_argument("--oracle-timing", action="store_true",
-                    help="also time the oracle single-threaded and on all threads on the small workloads")
+    ap.add_argument("--no-oracle-timing", action="store_true",
+                    help="skip timing the oracle single-threaded and on all threads on the small workloads")
     ap.add_argument("--variants", action="store_true", help="also time FP16/BF16/FP64 storage of the same field")
     ap.add_argument("--tile-width", type=int, default=None, help="tile width of the single-lattice kernels")
     ap.add_argument("--only-extra", choices=["cavity", "batch", "surrogate", "unet"],
@@ -400,11 +458,20 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.copy_calibration:
+        # 1 GiB copies: the runtime's, then the library's non-temporal copy probe
+        import ctypes as C
+
         import torch
+
+        from paper_1908_06742_amd import _lib as L
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(5):
             dst.copy_(src)
+        sp = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        for _ in range(5):
+            L.check(L.lib().ddf_bandwidth_probe(L.PROBE_COPY, 1, 1, C.c_void_p(src.data_ptr()),
+                                                C.c_void_p(dst.data_ptr()), 1 << 30, sp))
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read_per_dispatch": 1 << 30, "copy_bytes_written_per_dispatch": 1 << 30}))
         return
@@ -422,12 +489,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     print(f"[bench] {args.size}^2 {args.storage}: warmup {args.warmup}, timed {args.steps} steps "
           f"x {LB_STEPS_PER_STEP} LB steps", file=sys.stderr, flush=True)
-    r = run_gpu(args.size, args.storage, args.steps, args.warmup, tile_width=args.tile_width)
+    r = run_gpu(args.size, args.storage, args.steps, args.warmup, tile_width=args.tile_width, parity_steps=True)
     nodes = r["nodes"]
     bpn = BYTES_PER_NODE[args.storage]
     achieved = bpn * nodes / (r["kernel_ms"] * 1e-3) / 1e9
     traffic = measured_traffic(nodes, r["tile_width"]) if args.storage == "f32" and args.size == 8192 else None
-    cgbs = copy_gbs()
+    ceil = stream_ceilings()
+    cgbs = ceil["copy_gbs"]
     line = {
         "metric": "MLUPS (fluid+scalar D2Q9 node-updates per second / 1e6)",
         "value": round(r["mlups"], 1),
@@ -458,10 +526,15 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": bpn * nodes,
             "kernel_ms_per_launch": round(r["kernel_ms"], 4),
+            "kernel_ms_even": round(r["parity_ms"][0], 4),
+            "kernel_ms_odd": round(r["parity_ms"][1], 4),
+            "gbs_even": round(bpn * nodes / (r["parity_ms"][0] * 1e-3) / 1e9, 1),
+            "gbs_odd": round(bpn * nodes / (r["parity_ms"][1] * 1e-3) / 1e9, 1),
             "tile_width": r["tile_width"],
             "launch": r["launch"],
-            "copy_gbs": round(cgbs, 1),
+            "copy_gbs": cgbs,
             "frac_of_copy": round(achieved / cgbs, 4),
+            "stream_ceilings": ceil,
         },
         "final_stats": {k: r["stats"][k] for k in ("mass", "scalar", "res_u", "nonfinite")},
     }
@@ -499,7 +572,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline()
-        if args.oracle_timing:
+        if not args.no_oracle_timing:
             print("[bench] oracle timing (single thread and all threads)", file=sys.stderr, flush=True)
             line["cpu_baseline"]["oracle_timing"] = oracle_timing()
     print(json.dumps(line), flush=True)

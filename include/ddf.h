@@ -80,6 +80,20 @@ enum {
     DDF_NUM_OUTPUTS
 };
 
+/* Row layout of the population planes of a single lattice.  Row-major: node x of a row
+ * at column x.  x-interleaved: the row is 64 sub-rows of Q = nx / 64 nodes, node x at
+ * column (x mod 64) Q + x / 64, so the 64 nodes of a wavefront are consecutive in
+ * memory and their x +- 1 neighbours sit at the same lanes of the adjacent sub-row
+ * (whole aligned cache lines in both streaming parities; the step kernels then load and
+ * store non-temporally).  It needs nx = 64 * 2^k with nx / 64 at least one 128-byte line
+ * of the storage type (nx >= 1024 in F64, 2048 in F32, 4096 in 16-bit storage).  AUTO
+ * takes it for such lattices whose two population arrays exceed 256 MB (they stream from
+ * HBM), else row-major.  The layout is internal: every entry point reads and writes
+ * fields and populations in the logical [ny][nx] order either way, and results are the
+ * same bit for bit (reduction sums up to their summation order).  Batches are row-major
+ * (DDF_ERR_UNSUPPORTED for INTERLEAVED). */
+enum { DDF_LAYOUT_AUTO = 0, DDF_LAYOUT_ROW = 1, DDF_LAYOUT_INTERLEAVED = 2 };
+
 /* Statistics returned by ddf_reduce (all from one FP64 pass over the state). */
 enum {
     DDF_STAT_MASS = 0,        /* sum of rho */
@@ -107,7 +121,7 @@ typedef struct {
     double wall_u[4][2];         /* wall velocity per side (DDF_SIDE_*); used where that side is a wall */
     double wall_phi[4];          /* Dirichlet scalar per side; NaN = zero-flux wall */
     int32_t force_kind;          /* DDF_FORCE_* */
-    int32_t reserved0;
+    int32_t layout;              /* DDF_LAYOUT_*: row layout of the population planes (single lattices) */
     double force[2];
     double force_k;
     double force_omega;
@@ -131,9 +145,10 @@ size_t ddf_population_bytes(const ddf_params *p);
 size_t ddf_workspace_bytes(const ddf_params *p);
 
 /* Validate p (tau > 1/2 equivalents: 0 < omega < 2 for omega3..8 and omega1^phi..8^phi,
- * beta1 != beta2, nx, ny >= 2, known storage/model/force) and bind the caller's
+ * beta1 != beta2, nx, ny >= 2, known storage/model/force/layout) and bind the caller's
  * buffers.  pop_f, pop_g: ddf_population_bytes(p) each; workspace:
- * ddf_workspace_bytes(p); all 256-byte aligned.  *out receives the handle. */
+ * ddf_workspace_bytes(p); all 256-byte aligned.  *out receives the handle.
+ * DDF_ERR_UNSUPPORTED for DDF_LAYOUT_INTERLEAVED on a width that does not allow it. */
 int ddf_create(const ddf_params *p, void *pop_f, void *pop_g, void *workspace, ddf_handle **out);
 void ddf_destroy(ddf_handle *h);
 
@@ -204,6 +219,9 @@ int ddf_get_workgroups_per_cu(const ddf_handle *h, int32_t *even, int32_t *odd);
  * steps_per_graph > 0.  Changing the tiling or the run length drops the captured graph
  * (after waiting for the device). */
 int ddf_set_graph(ddf_handle *h, int32_t steps_per_graph);
+
+/* DDF_LAYOUT_ROW or DDF_LAYOUT_INTERLEAVED: the layout ddf_create chose. */
+int32_t ddf_get_layout(const ddf_handle *h);
 
 int64_t ddf_step_count(const ddf_handle *h);
 const char *ddf_last_error(void);

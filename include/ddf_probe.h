@@ -1,0 +1,39 @@
+/*
+ * ddf_probe.h - HBM reference kernels of libddf (MI355X, gfx950).
+ *
+ * Not part of the paper's method: these are the bandwidth ceilings the lattice
+ * Boltzmann step kernels are measured against.  The step is bound by HBM bandwidth
+ * (it reads and writes every population once per time step and does 1-2 flops per
+ * byte), so its achieved GB/s is compared with the nominal HBM peak and with what a
+ * plain stream reaches on the same device: a copy (each byte read once and written
+ * once, like the step), a read-only and a write-only pass.
+ *
+ * Conventions: as in ddf.h (caller-owned device buffers, asynchronous on `stream`,
+ * DDF_OK or a negative ddf_status, message in ddf_last_error()).
+ */
+#ifndef DDF_PROBE_H
+#define DDF_PROBE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { DDF_PROBE_COPY = 0, DDF_PROBE_READ = 1, DDF_PROBE_WRITE = 2 };
+
+/* One pass over `bytes` bytes (a positive multiple of 16; src and dst 16-byte aligned):
+ *   DDF_PROBE_COPY : dst[i] = src[i]            (reads and writes `bytes`)
+ *   DDF_PROBE_READ : reads src, writes nothing   (dst is not touched and may be NULL)
+ *   DDF_PROBE_WRITE: dst[i] = 0                  (src is not read and may be NULL)
+ * Each thread of a 256-thread workgroup moves `unroll` (1, 2, 4 or 8) 16-byte vectors
+ * 4 KiB apart; nontemporal != 0 marks the loads and stores non-temporal.  src and dst
+ * must not overlap.  DDF_ERR_ARG for anything else. */
+int ddf_bandwidth_probe(int32_t kind, int32_t unroll, int32_t nontemporal, const void *src, void *dst, size_t bytes,
+                        void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDF_PROBE_H */

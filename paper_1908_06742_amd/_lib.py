@@ -21,6 +21,8 @@ STATUS_NAMES = {0: "DDF_OK", -1: "DDF_ERR_ARG", -2: "DDF_ERR_UNSUPPORTED", -3: "
                 -4: "DDF_ERR_NONFINITE", -5: "DDF_ERR_STATE"}
 
 FORCE = {"none": 0, "uniform": 1, "fourroll": 2, "pulsatile": 3}
+LAYOUT = {"auto": 0, "row": 1, "interleaved": 2}
+LAYOUT_NAMES = {1: "row", 2: "interleaved"}
 SCALAR = {"mrt": 0, "srt": 1, "cascaded": 2, "central": 3}
 
 OUTPUTS = ("rho", "ux", "uy", "phi", "Sxx", "Syy", "Sxy", "wz",
@@ -44,7 +46,7 @@ class Params(C.Structure):
         ("cs2", C.c_double), ("cs2_phi", C.c_double),
         ("wall_u", (C.c_double * 2) * 4),
         ("wall_phi", C.c_double * 4),
-        ("force_kind", C.c_int32), ("reserved0", C.c_int32),
+        ("force_kind", C.c_int32), ("layout", C.c_int32),
         ("force", C.c_double * 2),
         ("force_k", C.c_double), ("force_omega", C.c_double),
         ("rho0", C.c_double), ("phi0", C.c_double),
@@ -69,6 +71,7 @@ SIGNATURES = {
     "ddf_get_populations": (C.c_int, [_vp, _vp, _vp, C.c_int32, _vp]),
     "ddf_set_populations": (C.c_int, [_vp, _vp, _vp, C.c_int32, C.c_int64, _vp]),
     "ddf_step_count": (C.c_int64, [_vp]),
+    "ddf_get_layout": (C.c_int32, [_vp]),
     "ddf_set_tile_width": (C.c_int, [_vp, C.c_int32]),
     "ddf_get_tile_width": (C.c_int32, [_vp]),
     "ddf_set_address_width": (C.c_int, [_vp, C.c_int32]),
@@ -135,6 +138,10 @@ NN_SIGNATURES = {
 }
 SIGNATURES.update(NN_SIGNATURES)
 
+# include/ddf_probe.h
+PROBE_COPY, PROBE_READ, PROBE_WRITE = 0, 1, 2
+SIGNATURES["ddf_bandwidth_probe"] = (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _vp, _vp, C.c_size_t, _vp])
+
 _lib = None
 
 
@@ -184,4 +191,5 @@ def params_from_problem(pr) -> Params:
     p.rho0, p.phi0 = pr.rho0, pr.phi0
     p.pop_scale = getattr(pr, "pop_scale", 0.0) or 0.0
     p.phi_min = pr.phi_min
+    p.layout = LAYOUT[getattr(pr, "layout", "auto")]
     return p

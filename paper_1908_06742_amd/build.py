@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", n) for n in ("ddf.hip", "ddf_batch.hip", "ddf_nn.hip")]
+SOURCES = [os.path.join(HERE, "csrc", n) for n in ("ddf.hip", "ddf_step_row.hip", "ddf_step_il.hip", "ddf_batch.hip", "ddf_nn.hip", "ddf_probe.hip")]
 LIB = os.path.join(HERE, "libddf.so")
 
 HIPCC_FLAGS = [

@@ -1,98 +1,12 @@
 // libddf, single-lattice entry points: fused two-lattice DDF lattice Boltzmann step,
 // local kinematics extraction and FP64 reductions for MI355X (gfx950), behind the
 // C ABI declared in include/ddf.h.  Kernels and layout: ddf_kernels.hpp.
-#include "ddf_kernels.hpp"
+#include "ddf_handle.hpp"
 
 using namespace ddf;
 using namespace ddf::host;
 
-struct ddf_handle {
-    ddf_params p;
-    void *f, *g, *ws;
-    Geom G;
-    int tile_width;
-    int nblocks;
-    bool idx32;            // step kernels with 32-bit lane offsets (planes below 4 GiB)
-    int wg_cap[2];         // resident step workgroups per CU, even / odd step (0 = no limit)
-    int64_t step;
-    int64_t snap_step;
-    bool snap_valid;
-    bool initialised;
-    PhysPair P;
-    // runs of graph_steps steps are captured once into a hipGraph on cap_stream and
-    // replayed on the caller's stream
-    hipStream_t cap_stream;
-    hipGraphExec_t graph_exec;
-    int graph_steps;       // even; 0 = always launch eagerly
-    int captured_steps;    // steps of the instantiated graph, 0 = none
-};
-
 namespace {
-
-// Dynamic LDS that limits a 512-thread workgroup of a kernel using no LDS to `cap`
-// resident workgroups per CU (0: no limit).  The CU's LDS size is read once.
-int cap_lds_bytes(int cap)
-{
-    static const int lds_cu = [] {
-        int dev = 0, v = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
-            v = 0;
-        return v;
-    }();
-    if (cap <= 0 || lds_cu <= 0) return 0;
-    return (lds_cu / (cap + 1) + 512) / 512 * 512;   // cap of them fit, cap + 1 do not
-}
-
-template <class S, int SC, bool W, bool FO, bool I32>
-void launch_step_kernel(ddf_handle *h, hipStream_t st, bool odd, int64_t t)
-{
-    const auto &P = h->P.of<S>();
-    const int lds = cap_lds_bytes(h->wg_cap[odd ? 1 : 0]);
-    if (odd)
-        hipLaunchKernelGGL((k_step<S, SC, W, FO, true, I32>), dim3(h->nblocks), dim3(kThreads), lds, st, (S *)h->f,
-                           (S *)h->g, h->G, P, t);
-    else
-        hipLaunchKernelGGL((k_step<S, SC, W, FO, false, I32>), dim3(h->nblocks), dim3(kThreads), lds, st, (S *)h->f,
-                           (S *)h->g, h->G, P, t);
-}
-
-template <class S, int SC, bool W, bool FO>
-void launch_step_parity(ddf_handle *h, hipStream_t st, bool odd, int64_t t)
-{
-    if (h->idx32) launch_step_kernel<S, SC, W, FO, true>(h, st, odd, t);
-    else launch_step_kernel<S, SC, W, FO, false>(h, st, odd, t);
-}
-
-template <class S, int SC>
-void launch_step(ddf_handle *h, hipStream_t st, int64_t t)
-{
-    const bool odd = (t & 1) != 0;
-    const bool w = has_walls(h->p);
-    const bool fo = h->p.force_kind != DDF_FORCE_NONE;
-    if (w) {
-        if (fo) launch_step_parity<S, SC, true, true>(h, st, odd, t);
-        else launch_step_parity<S, SC, true, false>(h, st, odd, t);
-    } else {
-        if (fo) launch_step_parity<S, SC, false, true>(h, st, odd, t);
-        else launch_step_parity<S, SC, false, false>(h, st, odd, t);
-    }
-}
-
-// One step of time index t (its parity selects the streaming direction).
-void launch_one(ddf_handle *h, hipStream_t st, int64_t t)
-{
-    with_storage(h->p.storage, [&](auto *tag) {
-        using S = std::remove_pointer_t<decltype(tag)>;
-        switch (h->p.scalar_model) {
-        case DDF_SCALAR_SRT: launch_step<S, DDF_SCALAR_SRT>(h, st, t); break;
-        case DDF_SCALAR_CASCADED:
-        case DDF_SCALAR_CENTRAL: launch_step<S, DDF_SCALAR_CENTRAL>(h, st, t); break;
-        default: launch_step<S, DDF_SCALAR_MRT>(h, st, t);
-        }
-        return 0;
-    });
-}
 
 // Kernels take the time index as an argument, which a captured graph freezes: lattices
 // whose step depends on it (a time-dependent force, stochastic rounding keys) run eagerly.
@@ -148,7 +62,9 @@ int ddf_set_tile_width(ddf_handle *h, int32_t bx_max)
     if (h->captured_steps) DDF_HIP_TRY(hipDeviceSynchronize());   // a replay may still be running
     drop_graph(h);
     h->tile_width = bx_max;
+    const int qs = h->G.L.qs;
     h->G = make_geom(h->p, bx_max);
+    h->G.L.qs = qs;
     h->nblocks = grid_blocks(h->G);
     return DDF_OK;
 }
@@ -170,11 +86,26 @@ bool plane_fits_32(const ddf_handle *h)
 // cavity step and the stochastic-rounding codec need every wavefront to hide their
 // latency (the FP16 cavity step was 13% slower with caps).  Lattices held by the
 // cache keep every wavefront.
+//
+// x-interleaved rows (non-temporal accesses; every cap pair and both offset widths):
+// on the 8192^2 field FP32 2 / 2 (6.0 TB/s), FP64 1 / 1 (5.4 TB/s), FP16 3 / 2 and BF16
+// 3 / 3 with 64-bit offsets (5.7-5.8 TB/s), BF16 with stochastic rounding 3 / 0
+// (5.5 TB/s); on an 8192^2 cavity FP32 2 / 2 (6.1 TB/s), FP64 1 / 1 (4.8 TB/s) and the
+// 16-bit formats 3 / 0 (5.6 TB/s).
 void launch_defaults(ddf_handle *h)
 {
     h->idx32 = plane_fits_32(h);
     h->wg_cap[0] = h->wg_cap[1] = 0;
     if (2 * population_bytes(&h->p) <= (size_t)256 << 20) return;
+    if (h->G.L.qs) {
+        static const int caps[5][2] = {{1, 1}, {2, 2}, {3, 2}, {3, 3}, {3, 0}};   // by ddf_storage
+        const bool sixteen = h->p.storage == DDF_F16 || h->p.storage == DDF_BF16;
+        const bool walls = has_walls(h->p);
+        h->wg_cap[0] = caps[h->p.storage][0];
+        h->wg_cap[1] = sixteen && walls ? 0 : caps[h->p.storage][1];
+        if (sixteen && !walls) h->idx32 = false;
+        return;
+    }
     if (h->p.storage == DDF_F32) {
         h->wg_cap[0] = h->wg_cap[1] = has_walls(h->p) ? 2 : 1;
     } else if (h->p.storage == DDF_F64) {
@@ -230,6 +161,14 @@ int ddf_create(const ddf_params *p, void *pop_f, void *pop_g, void *workspace, d
     if (!pop_f || !pop_g || !workspace) return fail(DDF_ERR_ARG, "a device buffer is NULL");
     if (((uintptr_t)pop_f | (uintptr_t)pop_g | (uintptr_t)workspace) & 255)
         return fail(DDF_ERR_ARG, "device buffers must be 256-byte aligned");
+    // Row layout: x-interleaved rows where the width allows them and the lattice streams
+    // from HBM (AUTO), or as requested.
+    int qs = interleave_shift(*p);
+    if (p->layout == DDF_LAYOUT_INTERLEAVED && qs == 0)
+        return fail(DDF_ERR_UNSUPPORTED, "x-interleaved rows need nx = 64 * 2^k with nx / 64 >= one 128-byte line "
+                                         "of the storage type");
+    if (p->layout == DDF_LAYOUT_ROW || (p->layout == DDF_LAYOUT_AUTO && 2 * population_bytes(p) <= (size_t)256 << 20))
+        qs = 0;
     ddf_handle *h = new (std::nothrow) ddf_handle;
     if (!h) return fail(DDF_ERR_ARG, "out of host memory");
     h->p = *p;
@@ -240,6 +179,7 @@ int ddf_create(const ddf_params *p, void *pop_f, void *pop_g, void *workspace, d
     // cavities: up to 3.9% against the HBM-streaming defaults below; never slower).
     h->tile_width = 2 * population_bytes(p) <= (size_t)256 << 20 ? 512 : default_tile_width(p->storage);
     h->G = make_geom(*p, h->tile_width);
+    h->G.L.qs = qs;
     h->nblocks = grid_blocks(h->G);
     launch_defaults(h);
     h->step = 0;
@@ -277,6 +217,8 @@ int ddf_set_graph(ddf_handle *h, int32_t steps_per_graph)
 }
 
 int32_t ddf_get_tile_width(const ddf_handle *h) { return h ? h->tile_width : 0; }
+
+int32_t ddf_get_layout(const ddf_handle *h) { return !h ? 0 : (h->G.L.qs ? DDF_LAYOUT_INTERLEAVED : DDF_LAYOUT_ROW); }
 
 int64_t ddf_step_count(const ddf_handle *h) { return h ? h->step : -1; }
 

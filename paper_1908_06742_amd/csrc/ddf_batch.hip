@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(S *__restrict__ f, S *_
         const auto &D = inst[tr.inst];
         int x, y;
         if (inst_node(D, tr.tile, x, y))
-            step_node<S, SCALAR, true, true, ODD>(f + D.off, g + D.off, D.L, D.P, x, y, t);
+            step_node<S, SCALAR, true, true, ODD, false, LY_ROW>(f + D.off, g + D.off, D.L, D.P, x, y, t);
         else if (D.bx_shift >= 6 && pad_slot<S>(D.L, x, y))   // rectangular tiles: x, y were set
             fill_pad(f + D.off, g + D.off, D.L, x, y);
     }
@@ -214,6 +214,8 @@ int validate_batch(int n, const ddf_params *ps)
         const int m0 = ps[0].scalar_model == DDF_SCALAR_CASCADED ? DDF_SCALAR_CENTRAL : ps[0].scalar_model;
         const int mi = ps[i].scalar_model == DDF_SCALAR_CASCADED ? DDF_SCALAR_CENTRAL : ps[i].scalar_model;
         if (mi != m0) return fail(DDF_ERR_ARG, "all batch instances must share one scalar collision model");
+        if (ps[i].layout == DDF_LAYOUT_INTERLEAVED)
+            return fail(DDF_ERR_UNSUPPORTED, "instance " + std::to_string(i) + ": batches keep row-major rows");
     }
     return DDF_OK;
 }

@@ -8,6 +8,16 @@
 // node touches at one (x, y) do not start at the same offset of the HBM channel
 // interleave (measured: +2% on 8192^2 FP32).
 //
+// Large lattices whose width is 64 * 2^k (k >= 5 for 4-byte storage) may instead keep
+// each row x-interleaved: memory column m of a row holds node x = (m mod Q) * 64 + m / Q
+// with Q = nx / 64, i.e. the row is 64 sub-rows of Q nodes, 64 apart in x.  A wavefront
+// then handles 64 nodes that are consecutive in memory and 64 apart in x, so their
+// x +- 1 neighbours sit at the same lanes of the adjacent sub-row: every population
+// access of both parities is a whole, aligned 128-byte line group, except at the
+// sub-row wrap (one sub-row pair in 64).  With aligned accesses the step kernels also
+// mark their loads and stores non-temporal (measured on the 8192^2 FP32 field: 6.0 TB/s
+// against 5.6 TB/s for the row-major step).
+//
 // Streaming is the in-place AA pattern: an even step reads a node's own slots and
 // writes its post-collision populations into the opposite slots of the same node; an
 // odd step reads the slots its neighbours wrote and pushes its results into their
@@ -39,7 +49,26 @@ struct Lat {
     int pitch;          // elements per row
     int64_t plane;      // elements per direction plane
     int px, py;         // periodic flags
+    int qs;             // x-interleaved rows: log2(nx / 64); 0 = row-major
 };
+
+// Row layouts, as template arguments: row-major, x-interleaved, or read from Lat::qs.
+enum { LY_ROW = 0, LY_IL = 1, LY_ANY = 2 };
+
+// Memory column of node x in its row, and the node of memory column m.
+template <int LY>
+__device__ __forceinline__ int col_of(const Lat &L, int x)
+{
+    if (LY == LY_ROW || (LY == LY_ANY && L.qs == 0)) return x;
+    return ((x & 63) << L.qs) | (x >> 6);
+}
+
+template <int LY>
+__device__ __forceinline__ int x_of(const Lat &L, int m)
+{
+    if (LY == LY_ROW || (LY == LY_ANY && L.qs == 0)) return m;
+    return ((m & ((1 << L.qs) - 1)) << 6) | (m >> L.qs);
+}
 
 // One lattice tiled into workgroups of kThreads threads, bx = 1 << bx_shift wide.
 struct Geom {
@@ -96,11 +125,16 @@ __device__ __forceinline__ void fill_pad(S *__restrict__ f, S *__restrict__ g, c
     }
 }
 
+// Node (x, y) of this thread: tiles cover memory columns, so consecutive lanes touch
+// consecutive population slots in either row layout.
 __device__ __forceinline__ bool node_of_thread(const Geom &G, int &x, int &y)
 {
     const int t = tile_of_block();
     if (t >= G.ntiles) return false;
-    return tile_node(t, G.bx_shift, G.by, G.tiles_x, G.L.nx, G.L.ny, x, y);
+    int m;
+    if (!tile_node(t, G.bx_shift, G.by, G.tiles_x, G.L.nx, G.L.ny, m, y)) return false;
+    x = x_of<LY_ANY>(G.L, m);
+    return true;
 }
 
 // Neighbour of (x, y) along (dx, dy) with periodic wrapping; returns the wall side
@@ -130,24 +164,24 @@ __device__ __forceinline__ int neighbour(const Lat &L, int x, int y, int dx, int
 // the population sits in the opposite slot of its source node, or (for a population
 // reflected by a wall) in slot a of the node itself.  Returns the cell and sets the
 // plane in *pa.
-template <bool WALLS, bool ODD>
+template <bool WALLS, bool ODD, int LY = LY_ANY>
 __device__ __forceinline__ int64_t logical_cell(const Lat &L, int x, int y, int a, int &pa)
 {
-    const int64_t cell = (int64_t)y * L.pitch + x;
+    const int64_t cell = (int64_t)y * L.pitch + col_of<LY>(L, x);
     pa = a;
     if (!ODD || a == 0) return cell;
     int sx, sy;
     const int w = neighbour<WALLS>(L, x, y, -ex(a), -ey(a), sx, sy);
     if (w >= 0) return cell;
     pa = opp(a);
-    return (int64_t)sy * L.pitch + sx;
+    return (int64_t)sy * L.pitch + col_of<LY>(L, sx);
 }
 
-template <bool WALLS, bool ODD>
+template <bool WALLS, bool ODD, int LY = LY_ANY>
 __device__ __forceinline__ int64_t logical_slot(const Lat &L, int x, int y, int a)
 {
     int pa;
-    const int64_t cell = logical_cell<WALLS, ODD>(L, x, y, a, pa);
+    const int64_t cell = logical_cell<WALLS, ODD, LY>(L, x, y, a, pa);
     return (int64_t)pa * L.plane + cell;
 }
 
@@ -165,27 +199,55 @@ __device__ __forceinline__ S &elem(S *__restrict__ base, const Lat &L, int pa, i
     return p[cell];
 }
 
-template <class S, bool WALLS, bool ODD, bool IDX32 = false>
+// Loads and stores of stored populations; NT marks them non-temporal (streamed: no
+// reuse expected in the caches).
+template <bool NT, class S>
+__device__ __forceinline__ S ld_pop(const S *p)
+{
+    if constexpr (!NT) {
+        return *p;
+    } else if constexpr (std::is_same<S, bf16>::value || std::is_same<S, bf16sr>::value) {
+        S r;
+        r.bits = __builtin_nontemporal_load(&p->bits);
+        return r;
+    } else {
+        return __builtin_nontemporal_load(p);
+    }
+}
+
+template <bool NT, class S>
+__device__ __forceinline__ void st_pop(S *p, S v)
+{
+    if constexpr (!NT) {
+        *p = v;
+    } else if constexpr (std::is_same<S, bf16>::value || std::is_same<S, bf16sr>::value) {
+        __builtin_nontemporal_store(v.bits, &p->bits);
+    } else {
+        __builtin_nontemporal_store(v, p);
+    }
+}
+
+template <class S, bool WALLS, bool ODD, bool IDX32 = false, int LY = LY_ANY, bool NT = false>
 __device__ __forceinline__ void load_logical(const S *__restrict__ f, const Lat &L, int x, int y,
                                              typename Codec<S>::R inv_scale, typename Codec<S>::R v[9])
 {
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         int pa;
-        const int64_t c = logical_cell<WALLS, ODD>(L, x, y, a, pa);
-        v[a] = Codec<S>::dec(elem<IDX32>(f, L, pa, c)) * inv_scale;
+        const int64_t c = logical_cell<WALLS, ODD, LY>(L, x, y, a, pa);
+        v[a] = Codec<S>::dec(ld_pop<NT>(&elem<IDX32>(f, L, pa, c))) * inv_scale;
     }
 }
 
 // One time step of node (x, y): load both lattices, collide, stream with walls.
-template <class S, int SCALAR, bool WALLS, bool FORCE, bool ODD, bool IDX32 = false>
+template <class S, int SCALAR, bool WALLS, bool FORCE, bool ODD, bool IDX32 = false, int LY = LY_ROW, bool NT = false>
 __device__ __forceinline__ void step_node(S *__restrict__ f, S *__restrict__ g, const Lat &L,
                                           const Phys<typename Codec<S>::R> &P, int x, int y, int64_t t)
 {
     using R = typename Codec<S>::R;
     R fv[9], gv[9];
-    load_logical<S, WALLS, ODD, IDX32>(f, L, x, y, P.inv_scale, fv);
-    load_logical<S, WALLS, ODD, IDX32>(g, L, x, y, P.inv_scale, gv);
+    load_logical<S, WALLS, ODD, IDX32, LY, NT>(f, L, x, y, P.inv_scale, fv);
+    load_logical<S, WALLS, ODD, IDX32, LY, NT>(g, L, x, y, P.inv_scale, gv);
 
     R m[9], n[9];
     moments(fv, m);
@@ -200,16 +262,17 @@ __device__ __forceinline__ void step_node(S *__restrict__ f, S *__restrict__ g, 
     else if (SCALAR == DDF_SCALAR_CENTRAL) collide_scalar_central(P, M, gv, go);
     else collide_scalar_mrt(P, M, n, go);
 
-    const int64_t cell = (int64_t)y * L.pitch + x;
+    const int64_t cell = (int64_t)y * L.pitch + col_of<LY>(L, x);
     // stochastic-rounding bits (codecs that round to nearest ignore them): keyed by the
-    // step, the node and the direction, which every step writes exactly once each
+    // step, the node and the direction, which every step writes exactly once each; the
+    // key names the node by its coordinates, so both row layouts store the same bits
     const uint32_t salt = sr_step_salt(t);
-    const int64_t key = 9 * cell;
+    const int64_t key = 9 * ((int64_t)y * L.pitch + x);
     // rest direction: same slot in both parities
     {
         const uint32_t h = sr_bits(key, salt);
-        elem<IDX32>(f, L, 0, cell) = Codec<S>::enc(fo[0] * P.scale, h);
-        elem<IDX32>(g, L, 0, cell) = Codec<S>::enc(go[0] * P.scale, h >> 16);
+        st_pop<NT>(&elem<IDX32>(f, L, 0, cell), Codec<S>::enc(fo[0] * P.scale, h));
+        st_pop<NT>(&elem<IDX32>(g, L, 0, cell), Codec<S>::enc(go[0] * P.scale, h >> 16));
     }
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
@@ -225,28 +288,30 @@ __device__ __forceinline__ void step_node(S *__restrict__ f, S *__restrict__ g, 
             if (P.wall_dirichlet[w]) vg = -vg + P.wall_g[w][a];
         } else if (ODD) {
             pa = a;
-            c = (int64_t)ty * L.pitch + tx;
+            c = (int64_t)ty * L.pitch + col_of<LY>(L, tx);
         }
         const uint32_t h = sr_bits(key + a, salt);
-        elem<IDX32>(f, L, pa, c) = Codec<S>::enc(vf * P.scale, h);
-        elem<IDX32>(g, L, pa, c) = Codec<S>::enc(vg * P.scale, h >> 16);
+        st_pop<NT>(&elem<IDX32>(f, L, pa, c), Codec<S>::enc(vf * P.scale, h));
+        st_pop<NT>(&elem<IDX32>(g, L, pa, c), Codec<S>::enc(vg * P.scale, h >> 16));
     }
 }
 
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-template <class S, int SCALAR, bool WALLS, bool FORCE, bool ODD, bool IDX32>
+// The fused step over one lattice.  LY_IL (x-interleaved rows, which have no padding)
+// always runs with non-temporal loads and stores; LY_ROW never does.
+template <class S, int SCALAR, bool WALLS, bool FORCE, bool ODD, bool IDX32, int LY>
 __global__ __launch_bounds__(kThreads) void k_step(S *__restrict__ f, S *__restrict__ g, const Geom G,
                                                    const Phys<typename Codec<S>::R> P, const int64_t t)
 {
     const int tile = tile_of_block();
     if (tile >= G.ntiles) return;
-    int x, y;
-    if (tile_node(tile, G.bx_shift, G.by, G.tiles_x, G.L.nx, G.L.ny, x, y))
-        step_node<S, SCALAR, WALLS, FORCE, ODD, IDX32>(f, g, G.L, P, x, y, t);
-    else if (G.bx_shift >= 6 && pad_slot<S>(G.L, x, y))
-        fill_pad(f, g, G.L, x, y);
+    int m, y;
+    if (tile_node(tile, G.bx_shift, G.by, G.tiles_x, G.L.nx, G.L.ny, m, y))
+        step_node<S, SCALAR, WALLS, FORCE, ODD, IDX32, LY, LY == LY_IL>(f, g, G.L, P, x_of<LY>(G.L, m), y, t);
+    else if (LY == LY_ROW && G.bx_shift >= 6 && pad_slot<S>(G.L, m, y))
+        fill_pad(f, g, G.L, m, y);
 }
 
 template <class S, bool WALLS, bool ODD, class O>
@@ -273,6 +338,68 @@ __global__ __launch_bounds__(kThreads) void k_extract(const S *__restrict__ f, c
 #pragma unroll
     for (int k = 0; k < DDF_NUM_OUTPUTS; ++k)
         if (mask & (1u << k)) out[(int64_t)k * N + c] = (O)vals[k];
+}
+
+// Extraction over x-interleaved rows.  A workgroup takes 64 K consecutive nodes of one
+// row (K = 2^KS = 32, or 16 for rows of 1024 nodes): memory columns k0 .. k0 + K - 1 of
+// all 64 sub-rows, K / 8 nodes per thread, so each wavefront's population loads are runs
+// of K consecutive slots (whole 128-byte lines in FP32).  The outputs are staged through
+// LDS, four planes at a time, and stored in x order in runs of 64 K nodes.
+template <class S, bool WALLS, bool ODD, class O, int KS>
+__global__ __launch_bounds__(kThreads) void k_extract_il(const S *__restrict__ f, const S *__restrict__ g, const Lat L,
+                                                         const Phys<typename Codec<S>::R> P, const int64_t t,
+                                                         const int scalar_model, O *__restrict__ out, const uint32_t mask)
+{
+    using R = typename Codec<S>::R;
+    constexpr int K = 1 << KS, NODES = 64 * K, NPT = NODES / kThreads;
+    __shared__ O st[4][NODES];
+    const int per_row = L.nx / NODES;
+    const int y = blockIdx.x / per_row;
+    const int X0 = (blockIdx.x - y * per_row) * NODES;
+    O vals[NPT][DDF_NUM_OUTPUTS];
+    int xl[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int i = j * kThreads + (int)threadIdx.x;
+        const int sr = i >> KS, kk = i & (K - 1);   // sub-row, column within the run
+        xl[j] = (kk << 6) + sr;                      // node x - X0
+        const int x = X0 + xl[j];
+        R fv[9], gv[9], m[9], n[9];
+        load_logical<S, WALLS, ODD, false, LY_IL>(f, L, x, y, P.inv_scale, fv);
+        load_logical<S, WALLS, ODD, false, LY_IL>(g, L, x, y, P.inv_scale, gv);
+        moments(fv, m);
+        moments(gv, n);
+        R Fx = (R)0, Fy = (R)0;
+        body_force(P, x, y, t, Fx, Fy);
+        const Macro<R> M = macro(P, m, n, Fx, Fy);
+        const Kin<R> Kn = kinematics(P, M, m, n, Fx, Fy, scalar_model);
+        const R v[DDF_NUM_OUTPUTS] = {M.rho, M.ux, M.uy, M.phi, Kn.Sxx, Kn.Syy, Kn.Sxy, Kn.wz,
+                                      Kn.dxuy, Kn.dyux, Kn.dxphi, Kn.dyphi, Kn.Q, Kn.Rinv, Kn.Lx, Kn.Ly};
+#pragma unroll
+        for (int k = 0; k < DDF_NUM_OUTPUTS; ++k) vals[j][k] = (O)v[k];
+    }
+    const int64_t N = (int64_t)L.nx * L.ny;
+    const int64_t row = (int64_t)y * L.nx + X0;
+#pragma unroll
+    for (int grp = 0; grp < DDF_NUM_OUTPUTS / 4; ++grp) {
+        if (!((mask >> (4 * grp)) & 15u)) continue;
+#pragma unroll
+        for (int j = 0; j < NPT; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) st[q][xl[j]] = vals[j][4 * grp + q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = 4 * grp + q;
+            if (!(mask & (1u << k))) continue;
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                const int xi = j * kThreads + (int)threadIdx.x;
+                out[(int64_t)k * N + row + xi] = st[q][xi];
+            }
+        }
+        __syncthreads();
+    }
 }
 
 template <class S>
@@ -304,12 +431,13 @@ __global__ __launch_bounds__(kThreads) void k_init(S *__restrict__ f, S *__restr
     populations(e, fo);
     scalar_eq(P, M, n);
     populations(n, go);
-    const int64_t cell = (int64_t)y * G.L.pitch + x;
+    const int64_t node = (int64_t)y * G.L.pitch + x;
+    const int64_t cell = (int64_t)y * G.L.pitch + col_of<LY_ANY>(G.L, x);
     const uint32_t salt = sr_step_salt(-1);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         const int64_t s = (int64_t)a * G.L.plane + cell;
-        const uint32_t h = sr_bits(s, salt);
+        const uint32_t h = sr_bits((int64_t)a * G.L.plane + node, salt);   // same bits in either row layout
         f[s] = Codec<S>::enc(fo[a] * P.scale, h);
         g[s] = Codec<S>::enc(go[a] * P.scale, h >> 16);
     }
@@ -352,8 +480,9 @@ __device__ __forceinline__ void node_stats(const S *__restrict__ f, const S *__r
     R Fx = (R)0, Fy = (R)0;
     body_force(P, x, y, t, Fx, Fy);
     const Macro<R> M = macro(P, m, n, Fx, Fy);
+    // the residual snapshot is private: kept in the populations' column order
     const int64_t N = (int64_t)L.nx * L.ny;
-    const int64_t c = (int64_t)y * L.nx + x;
+    const int64_t c = (int64_t)y * L.nx + col_of<LY_ANY>(L, x);
     const double ux = (double)M.ux, uy = (double)M.uy, phi = (double)M.phi;
     v[RS_MASS] = (double)P.rho0 + (double)M.drho;
     v[RS_SCALAR] = (double)P.phi0 + (double)M.dphi;
@@ -457,7 +586,8 @@ __global__ __launch_bounds__(kThreads) void k_set(S *__restrict__ f, S *__restri
         if (dtype == 0) {
             const double vf = ((const double *)fi)[a * N + c] - (double)P.rest_f[a] * (double)P.rho0;
             const double vg = ((const double *)gi)[a * N + c] - (double)P.rest_g[a] * (double)P.phi0;
-            const uint32_t h = sr_bits(s, sr_step_salt(-2));
+            // keyed by the slot's row-major index: the same bits in either row layout
+            const uint32_t h = sr_bits(logical_slot<WALLS, ODD, LY_ROW>(G.L, x, y, a), sr_step_salt(-2));
             f[s] = Codec<S>::enc((R)(vf * (double)P.scale), h);
             g[s] = Codec<S>::enc((R)(vg * (double)P.scale), h >> 16);
         } else {
@@ -603,6 +733,7 @@ inline Lat make_lat(const ddf_params &p)
     L.plane = plane_of(&p);
     L.px = p.periodic_x ? 1 : 0;
     L.py = p.periodic_y ? 1 : 0;
+    L.qs = 0;   // row-major; a single lattice may switch to x-interleaved rows (interleave_shift)
     return L;
 }
 
@@ -652,6 +783,7 @@ inline int validate(const ddf_params *p)
     if (!(std::fabs(p->beta1 - p->beta2) > 1e-12)) return fail(DDF_ERR_ARG, "beta1 == beta2: the vorticity relation is singular");
     if (!(p->cs2 > 0.0) || !(p->cs2_phi > 0.0)) return fail(DDF_ERR_ARG, "cs2 and cs2_phi must be positive");
     if (!(p->rho0 > 0.0)) return fail(DDF_ERR_ARG, "rho0 must be positive");
+    if (p->layout < DDF_LAYOUT_AUTO || p->layout > DDF_LAYOUT_INTERLEAVED) return fail(DDF_ERR_ARG, "unknown layout");
     if (p->pop_scale < 0.0) return fail(DDF_ERR_ARG, "pop_scale must be >= 0");
     if (p->pop_scale > 0.0) {
         int e;
@@ -661,6 +793,17 @@ inline int validate(const ddf_params *p)
 }
 
 inline bool has_walls(const ddf_params &p) { return !(p.periodic_x && p.periodic_y); }
+
+// log2(nx / 64) when rows of this lattice can be x-interleaved (nx = 64 * 2^k, and a
+// sub-row of nx / 64 nodes holds at least one 128-byte line of the storage type), else 0.
+inline int interleave_shift(const ddf_params &p)
+{
+    const int64_t q = p.nx / 64, line = 128 / (int64_t)storage_size(p.storage);
+    if (p.nx % 64 || q < line || (q & (q - 1))) return 0;
+    int qs = 0;
+    while (((int64_t)1 << qs) < q) ++qs;
+    return qs;
+}
 
 // Calls fn with a null pointer of the storage element type.
 template <class F>
@@ -695,6 +838,23 @@ void launch_extract(const Geom &G, const Phys<typename Codec<S>::R> &P, bool wal
     const int nb = grid_blocks(G);
     auto go = [&](auto *otag) {
         using O = std::remove_pointer_t<decltype(otag)>;
+        if (G.L.qs) {
+            // 2048-node runs; rows of 1024 nodes (FP64 only) take 1024-node runs
+            const int ks = G.L.nx % 2048 ? 4 : 5;
+            const dim3 grid((unsigned)((int64_t)(G.L.nx >> (6 + ks)) * G.L.ny));
+#define DDF_XI(W_, O_, KS_)                                                                                            \
+    hipLaunchKernelGGL((k_extract_il<S, W_, O_, O, KS_>), grid, dim3(kThreads), 0, st, (const S *)f, (const S *)g, G.L, P, \
+                       t, scalar_model, (O *)out, mask)
+            if (ks == 5) {
+                if (walls) { if (odd) DDF_XI(true, true, 5); else DDF_XI(true, false, 5); }
+                else { if (odd) DDF_XI(false, true, 5); else DDF_XI(false, false, 5); }
+            } else {
+                if (walls) { if (odd) DDF_XI(true, true, 4); else DDF_XI(true, false, 4); }
+                else { if (odd) DDF_XI(false, true, 4); else DDF_XI(false, false, 4); }
+            }
+#undef DDF_XI
+            return;
+        }
 #define DDF_X(W_, O_)                                                                                          \
     hipLaunchKernelGGL((k_extract<S, W_, O_, O>), dim3(nb), dim3(kThreads), 0, st, (const S *)f, (const S *)g, G, P, t, \
                        scalar_model, (O *)out, mask)

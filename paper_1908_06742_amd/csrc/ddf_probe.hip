@@ -1,0 +1,123 @@
+// libddf HBM reference kernels (include/ddf_probe.h): a copy, a read-only and a
+// write-only pass over a buffer, the ceilings the bandwidth-bound step kernels are
+// measured against.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/ddf.h"
+#include "../../include/ddf_probe.h"
+#include "ddf_kernels.hpp"
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kProbeThreads = 256;
+
+template <bool NT>
+__device__ __forceinline__ f4 ld(const f4 *p)
+{
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
+template <bool NT>
+__device__ __forceinline__ void st(f4 *p, f4 v)
+{
+    if (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// Workgroup b covers vectors [b * 256 U, (b + 1) * 256 U); thread t moves vectors
+// b * 256 U + k * 256 + t for k < U, so every load and store instruction of a wavefront
+// covers 1 KiB of consecutive bytes.  All loads of a thread are issued before its
+// stores (copy) or before the reduction that keeps them alive (read).
+template <int KIND, int U, bool NT>
+__global__ __launch_bounds__(kProbeThreads) void k_probe(const f4 *__restrict__ src, f4 *__restrict__ dst,
+                                                         const int64_t n4, const int keep)
+{
+    const int64_t base = (int64_t)blockIdx.x * (kProbeThreads * U) + threadIdx.x;
+    if (KIND == DDF_PROBE_WRITE) {
+        const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int64_t i = base + (int64_t)k * kProbeThreads;
+            if (i < n4) st<NT>(dst + i, z);
+        }
+        return;
+    }
+    f4 v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const int64_t i = base + (int64_t)k * kProbeThreads;
+        if (i < n4) v[k] = ld<NT>(src + i);
+        else v[k] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    if (KIND == DDF_PROBE_COPY) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int64_t i = base + (int64_t)k * kProbeThreads;
+            if (i < n4) st<NT>(dst + i, v[k]);
+        }
+    } else {
+        // the sum keeps the loads; the host passes keep = 0, so nothing is stored
+        f4 acc = v[0];
+#pragma unroll
+        for (int k = 1; k < U; ++k) acc += v[k];
+        if (keep) dst[base] = acc;
+    }
+}
+
+template <int KIND, int U>
+void launch_probe(bool nt, const void *src, void *dst, int64_t n4, hipStream_t st)
+{
+    const int64_t per = (int64_t)kProbeThreads * U;
+    const dim3 grid((unsigned)((n4 + per - 1) / per));
+    if (nt)
+        hipLaunchKernelGGL((k_probe<KIND, U, true>), grid, dim3(kProbeThreads), 0, st, (const f4 *)src, (f4 *)dst, n4, 0);
+    else
+        hipLaunchKernelGGL((k_probe<KIND, U, false>), grid, dim3(kProbeThreads), 0, st, (const f4 *)src, (f4 *)dst, n4, 0);
+}
+
+template <int KIND>
+void launch_kind(int unroll, bool nt, const void *src, void *dst, int64_t n4, hipStream_t st)
+{
+    switch (unroll) {
+    case 1: launch_probe<KIND, 1>(nt, src, dst, n4, st); break;
+    case 2: launch_probe<KIND, 2>(nt, src, dst, n4, st); break;
+    case 4: launch_probe<KIND, 4>(nt, src, dst, n4, st); break;
+    default: launch_probe<KIND, 8>(nt, src, dst, n4, st); break;
+    }
+}
+
+}  // namespace
+
+extern "C" int ddf_bandwidth_probe(int32_t kind, int32_t unroll, int32_t nontemporal, const void *src, void *dst,
+                                   size_t bytes, void *stream)
+{
+    using ddf::host::fail;
+    if (kind != DDF_PROBE_COPY && kind != DDF_PROBE_READ && kind != DDF_PROBE_WRITE)
+        return fail(DDF_ERR_ARG, "probe: kind must be DDF_PROBE_COPY, DDF_PROBE_READ or DDF_PROBE_WRITE");
+    if (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8)
+        return fail(DDF_ERR_ARG, "probe: unroll must be 1, 2, 4 or 8");
+    if (bytes == 0 || bytes % 16) return fail(DDF_ERR_ARG, "probe: bytes must be a positive multiple of 16");
+    if (kind != DDF_PROBE_WRITE && !src) return fail(DDF_ERR_ARG, "probe: src is NULL");
+    if (kind != DDF_PROBE_READ && !dst) return fail(DDF_ERR_ARG, "probe: dst is NULL");
+    if (((uintptr_t)src | (uintptr_t)dst) & 15) return fail(DDF_ERR_ARG, "probe: buffers must be 16-byte aligned");
+    const int64_t n4 = (int64_t)(bytes / 16);
+    if (n4 / (kProbeThreads * unroll) >= ((int64_t)1 << 31)) return fail(DDF_ERR_ARG, "probe: buffer too large");
+    if (kind == DDF_PROBE_COPY && src && dst) {
+        const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+        if (a < b + bytes && b < a + bytes) return fail(DDF_ERR_ARG, "probe: src and dst overlap");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const bool nt = nontemporal != 0;
+    if (kind == DDF_PROBE_COPY) launch_kind<DDF_PROBE_COPY>(unroll, nt, src, dst, n4, st);
+    else if (kind == DDF_PROBE_READ) launch_kind<DDF_PROBE_READ>(unroll, nt, src, dst, n4, st);
+    else launch_kind<DDF_PROBE_WRITE>(unroll, nt, src, dst, n4, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DDF_ERR_HIP, std::string("probe launch: ") + hipGetErrorString(e));
+    return DDF_OK;
+}

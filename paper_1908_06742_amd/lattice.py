@@ -144,6 +144,11 @@ class Lattice:
         return self
 
     @property
+    def layout(self):
+        """Row layout of the population planes ("row" or "interleaved"), chosen at creation."""
+        return L.LAYOUT_NAMES[int(L.lib().ddf_get_layout(self._h))]
+
+    @property
     def tile_width(self):
         return int(L.lib().ddf_get_tile_width(self._h))
 

@@ -51,7 +51,7 @@ def cmd_counters(args):
     write = counter_means(args.write, "WRITE_SIZE")
     cf = counter_means(args.copy_fetch, "FETCH_SIZE")
     cw = counter_means(args.copy_write, "WRITE_SIZE")
-    copy_name = [k for k in cf if "copyBuffer" in k][0]
+    copy_name = [k for k in cf if args.copy_kernel in k][0]
     copy_kib = 1 << 20   # 1 GiB read and written per copy dispatch
     f_scale = copy_kib / cf[copy_name][0]
     w_scale = copy_kib / cw[copy_name][0]
@@ -74,6 +74,7 @@ def cmd_counters(args):
         sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
         import bench
         json.dump({"kernel_hash": bench.kernel_hash(), "nodes": args.nodes, "tile_width": args.tile_width,
+                   "calibration_kernel": copy_name,
                    "bytes_per_launch": mean_total,
                    "algorithmic_bytes_per_launch": algo, "fetch_scale": f_scale, "write_scale": w_scale,
                    "per_parity": rows}, open(args.out, "w"), indent=1)
@@ -92,6 +93,8 @@ def main(argv=None):
     c.add_argument("copy_fetch")
     c.add_argument("copy_write")
     c.add_argument("--kernel", default="k_step")
+    c.add_argument("--copy-kernel", default="copyBuffer",
+                   help="calibration kernel (a 1 GiB copy): the runtime's copyBuffer or the library's k_probe")
     c.add_argument("--nodes", type=int, required=True)
     c.add_argument("--bytes-per-node", type=int, required=True)
     c.add_argument("--tile-width", type=int, required=True, help="tile width of the profiled lattice")

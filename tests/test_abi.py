@@ -13,7 +13,9 @@ from paper_1908_06742_amd import _lib as L
 
 def declared_functions():
     names = set()
-    for h in ("ddf.h", "ddf_nn.h"):
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
         src = open(os.path.join(ROOT, "include", h)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         names |= set(re.findall(r"\b(ddf_[a-z0-9_]+)\s*\(", src))
@@ -196,3 +198,60 @@ def test_batch_step_reduce_rejects_bad_arguments_before_any_launch():
     buf = (C.c_double * 8)()
     assert lib.ddf_batch_step_reduce(None, 2, buf, None) == L.DDF_ERR_ARG
     assert "NULL" in lib.ddf_last_error().decode()
+
+
+@pytest.mark.parametrize("args,needle", [
+    ((3, 4, 0, 1 << 20, 2 << 20, 1 << 20), "kind"),
+    ((0, 3, 0, 1 << 20, 2 << 20, 1 << 20), "unroll"),
+    ((0, 4, 0, 1 << 20, 2 << 20, 1000), "multiple of 16"),
+    ((0, 4, 0, 1 << 20, 2 << 20, 0), "multiple of 16"),
+    ((0, 4, 0, None, 2 << 20, 1 << 20), "src is NULL"),
+    ((2, 4, 0, None, None, 1 << 20), "dst is NULL"),
+    ((0, 4, 0, (1 << 20) + 8, 2 << 20, 1 << 20), "aligned"),
+    ((0, 4, 0, 1 << 20, (1 << 20) + 4096, 1 << 20), "overlap"),
+])
+def test_bandwidth_probe_rejects_invalid_arguments(args, needle):
+    kind, unroll, nt, src, dst, nbytes = args
+    rc = L.lib().ddf_bandwidth_probe(kind, unroll, nt, src, dst, nbytes, None)
+    assert rc == L.DDF_ERR_ARG and needle in L.lib().ddf_last_error().decode()
+
+
+def _create_rc(pr):
+    p = L.params_from_problem(pr)
+    h = C.c_void_p()
+    rc = L.lib().ddf_create(C.byref(p), C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20), C.byref(h))
+    layout = L.lib().ddf_get_layout(h) if rc == 0 else None
+    if rc == 0:
+        L.lib().ddf_destroy(h)
+    return rc, layout
+
+
+@pytest.mark.parametrize("storage,nx,ok", [
+    ("f64", 1024, True), ("f64", 512, False), ("f32", 2048, True), ("f32", 1024, False), ("f32", 3072, False),
+    ("f16", 4096, True), ("bf16", 2048, False), ("bf16sr", 8192, True), ("f32", 2000, False),
+])
+def test_interleaved_rows_need_a_power_of_two_width_of_whole_lines(storage, nx, ok):
+    # nx = 64 * 2^k and nx / 64 at least one 128-byte line of the storage type
+    rc, layout = _create_rc(W.Problem(nx=nx, ny=4, storage=storage, layout="interleaved"))
+    if ok:
+        assert rc == L.DDF_OK and layout == 2
+    else:
+        assert rc == L.DDF_ERR_UNSUPPORTED and "x-interleaved" in L.lib().ddf_last_error().decode()
+    rc, layout = _create_rc(W.Problem(nx=nx, ny=4, storage=storage, layout="row"))
+    assert rc == L.DDF_OK and layout == 1
+
+
+def test_automatic_layout_interleaves_only_lattices_beyond_the_cache():
+    # two population arrays above 256 MB stream from HBM and take interleaved rows
+    assert _create_rc(W.Problem(nx=8192, ny=8192, storage="f32"))[1] == 2
+    assert _create_rc(W.Problem(nx=8192, ny=8192, storage="bf16"))[1] == 2
+    assert _create_rc(W.Problem(nx=2048, ny=64, storage="f32"))[1] == 1       # in the cache
+    assert _create_rc(W.Problem(nx=8000, ny=8000, storage="f32"))[1] == 1     # width not 64 * 2^k
+    assert _create_rc(W.Problem(nx=32768, ny=32832, storage="f32"))[1] == 2   # 64-bit offsets
+
+
+def test_batches_keep_row_major_rows():
+    ps = (L.Params * 1)(L.params_from_problem(W.Problem(nx=2048, ny=4, storage="f32", layout="interleaved")))
+    h = C.c_void_p()
+    rc = L.lib().ddf_batch_create(1, ps, C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20), C.byref(h))
+    assert rc == L.DDF_ERR_UNSUPPORTED and "row-major" in L.lib().ddf_last_error().decode()
