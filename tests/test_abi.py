@@ -127,10 +127,13 @@ def test_workgroup_caps_default_by_storage_and_size():
     lib = L.lib()
     cav = lambda n, storage: W.cavity_problem(n, 1000.0, 0.1, storage=storage)
     per = lambda n, storage: W.Problem(nx=n, ny=n, storage=storage)
-    cases = [(per, "f32", 8192, (1, 1), 32), (per, "f16", 8192, (3, 2), 64), (per, "bf16", 8192, (3, 2), 64),
-             (per, "bf16sr", 8192, (0, 0), 32), (per, "f64", 8192, (1, 1), 32), (per, "f32", 1024, (0, 0), 32),
-             (cav, "f32", 8192, (2, 2), 32), (cav, "f16", 8192, (0, 0), 32), (cav, "f64", 8192, (1, 1), 32),
-             (per, "f64", 1024, (0, 0), 32)]
+    # 8192^2: x-interleaved rows; 8000^2: row-major rows; 1024^2: held by the cache
+    cases = [(per, "f32", 8192, (2, 2), 32), (per, "f16", 8192, (3, 2), 64), (per, "bf16", 8192, (3, 3), 64),
+             (per, "bf16sr", 8192, (3, 0), 32), (per, "f64", 8192, (1, 1), 32), (per, "f32", 1024, (0, 0), 32),
+             (cav, "f32", 8192, (2, 2), 32), (cav, "f16", 8192, (3, 0), 32), (cav, "f64", 8192, (1, 1), 32),
+             (per, "f64", 1024, (0, 0), 32),
+             (per, "f32", 8000, (1, 1), 32), (per, "f16", 8000, (3, 2), 64), (per, "bf16sr", 8000, (0, 0), 32),
+             (cav, "f32", 8000, (2, 2), 32), (cav, "f16", 8000, (0, 0), 32), (per, "f64", 8000, (1, 1), 32)]
     for make, storage, n, caps, bits in cases:
         p = L.params_from_problem(make(n, storage))
         h = C.c_void_p()
