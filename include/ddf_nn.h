@@ -79,6 +79,19 @@ size_t ddf_nn_mse_workspace_bytes(int64_t npix);
 int ddf_nn_mse(const void *out, int32_t o_cs, const float *target, int64_t npix, const float *weights4, void *dout,
                double *loss_dev, void *workspace, void *stream);
 
+/* ddf_nn_mse for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid hipMalloc): the same
+ * kernels and results, with the partial sums in a fixed 64 KiB device array of the
+ * library instead of a workspace, so npix is limited to ddf_nn_mse_static_max_pixels()
+ * (2,096,896; DDF_ERR_ARG beyond).  The call allocates nothing; its first call on a
+ * device looks the array up (hipGetSymbolAddress) with that device current.  Each GPU
+ * has one such array, shared by every call on it: calls that overlap on one GPU (on
+ * different streams, or from different threads) race and must be serialised by the
+ * caller. */
+size_t ddf_nn_mse_static_max_pixels(void);
+int ddf_nn_mse_static(const void *out, int32_t o_cs, const float *target, int64_t npix, const float *weights4,
+                      void *dout, double *loss_dev, void *stream);
+
 /* Adam with bias correction (step counts from 1) and decoupled-free L2 weight decay
  * added to the gradient. */
 int ddf_nn_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float beta1, float beta2, float eps,

@@ -129,6 +129,8 @@ NN_SIGNATURES = {
     "ddf_nn_slice": (C.c_int, [_vp, _i32, _i32, _vp, _i32, _i32, _i64, _i32, _i32, _vp]),
     "ddf_nn_mse_workspace_bytes": (C.c_size_t, [_i64]),
     "ddf_nn_mse": (C.c_int, [_vp, _i32, _vp, _i64, _fp, _vp, _vp, _vp, _vp]),
+    "ddf_nn_mse_static_max_pixels": (C.c_size_t, []),
+    "ddf_nn_mse_static": (C.c_int, [_vp, _i32, _vp, _i64, _fp, _vp, _vp, _vp]),
     "ddf_nn_adam": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _i64, _f32, _vp]),
     "ddf_nn_cast_weights": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp]),
     "ddf_nn_cast_weights_multi": (C.c_int, [_i32, C.POINTER(CastLayer), _vp]),

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdint>
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "../../include/ddf_nn.h"
@@ -695,9 +696,8 @@ __global__ __launch_bounds__(256) void k_mse(const __bf16 *__restrict__ out, int
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// out[0] = sum of part[0 .. n): thread t sums part[t], part[t + 256], ... in order, then a
-// fixed-order tree over the 256 thread sums (deterministic).
-// out[0] = (sum of part[0 .. n)) / div, in a fixed order.
+// out[0] = (sum of part[0 .. n)) / div: thread t sums part[t], part[t + 256], ... in order,
+// then a fixed-order tree over the 256 thread sums (deterministic).
 __global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ part, int n, double div,
                                                  double *__restrict__ out)
 {
@@ -1115,6 +1115,8 @@ int ddf_nn_mse(const void *out, int32_t o_cs, const float *target, int64_t npix,
                double *loss_dev, void *workspace, void *stream)
 {
     if (o_cs < 4) return fail(DDF_ERR_ARG, "mse: at least 4 output channels");
+    if (npix < 1 || npix > ((int64_t)1 << 40)) return fail(DDF_ERR_ARG, "mse: npix must be in [1, 2^40]");
+    if (!out || !target || !weights4 || !dout || !loss_dev || !workspace) return fail(DDF_ERR_ARG, "mse: null pointer");
     hipStream_t st = (hipStream_t)stream;
     const int nb = (int)((npix + 255) / 256);
     double *part = (double *)workspace;
@@ -1123,6 +1125,55 @@ int ddf_nn_mse(const void *out, int32_t o_cs, const float *target, int64_t npix,
                        weights4[1], weights4[2], weights4[3], (__bf16 *)dout, part, vec);
     hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, st, part, nb, (double)npix, loss_dev);
     return check_launch();
+}
+
+}  // extern "C"
+
+// ddf_nn_mse_static keeps its partial sums in this file-scope device array instead of a
+// caller workspace: one copy per GPU, held until the process ends.  In host code the
+// name stands for a host-side shadow, so kernels get the device address that
+// hipGetSymbolAddress returns for the current device (looked up once per device).
+constexpr size_t kMseScratchBytes = (size_t)64 << 10;
+static __device__ __align__(256) unsigned char scratch[kMseScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+int mse_scratch(void **ptr)
+{
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    DDF_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DDF_ERR_UNSUPPORTED, "mse_static: device index beyond 63");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        DDF_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(DDF_ERR_HIP, "mse_static: no device address for the scratch array");
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return DDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ddf_nn_mse_static_max_pixels(void) { return (kMseScratchBytes / sizeof(double) - 1) * 256; }
+
+int ddf_nn_mse_static(const void *out, int32_t o_cs, const float *target, int64_t npix, const float *weights4,
+                      void *dout, double *loss_dev, void *stream)
+{
+    if (npix > (int64_t)ddf_nn_mse_static_max_pixels() || ddf_nn_mse_workspace_bytes(npix) > kMseScratchBytes)
+        return fail(DDF_ERR_ARG, "mse_static: npix exceeds ddf_nn_mse_static_max_pixels() (" +
+                                     std::to_string(ddf_nn_mse_static_max_pixels()) + ")");
+    void *ws = nullptr;
+    const int rc = mse_scratch(&ws);
+    if (rc != DDF_OK) return rc;
+    return ddf_nn_mse(out, o_cs, target, npix, weights4, dout, loss_dev, ws, stream);
 }
 
 int ddf_nn_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float beta1, float beta2, float eps,
