@@ -265,9 +265,15 @@ int ddf_batch_init_equilibrium(ddf_batch *b, const double *rho, const double *ux
  * Results do not depend on the tiling.  Invalidates the captured graph. */
 int ddf_batch_set_tiling(ddf_batch *b, int32_t bx_max, int32_t blocks_per_cu);
 int ddf_batch_get_tiling(const ddf_batch *b, int32_t *bx_max, int32_t *blocks_per_cu, int32_t *ntiles, int32_t *grid);
+/* Non-temporal (streaming) loads and stores in the even and in the odd step kernel (0 or
+ * 1 each; default 0 / 0).  ddf_batch_autotune chooses them with the tiling.  Results do
+ * not depend on them; the call drops a captured graph (after waiting for the device). */
+int ddf_batch_set_nontemporal(ddf_batch *b, int32_t even, int32_t odd);
+int ddf_batch_get_nontemporal(const ddf_batch *b, int32_t *even, int32_t *odd);
 /* Times every (bx_max, blocks_per_cu) candidate (bx_max 0, 64, 128, 256 or 512) for
- * steps_per_trial steps on this instance mix, applies the fastest and caches it per
- * (storage, instance sizes) for the process.  The trials overwrite the populations: call it before
+ * steps_per_trial steps on this instance mix, then non-temporal accesses in either
+ * parity on the fastest, applies the best and caches it per (storage, scalar model,
+ * instance sizes and boundary kinds) for the process.  The trials overwrite the populations: call it before
  * ddf_batch_init_equilibrium.  best_ms_per_step is -1 when the cache answered. */
 int ddf_batch_autotune(ddf_batch *b, int32_t steps_per_trial, int32_t *bx_max, int32_t *blocks_per_cu,
                        float *best_ms_per_step, void *stream);

@@ -90,6 +90,8 @@ SIGNATURES = {
     "ddf_batch_init_equilibrium": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "ddf_batch_set_tiling": (C.c_int, [_vp, C.c_int32, C.c_int32]),
     "ddf_batch_get_tiling": (C.c_int, [_vp] + [C.POINTER(C.c_int32)] * 4),
+    "ddf_batch_set_nontemporal": (C.c_int, [_vp, C.c_int32, C.c_int32]),
+    "ddf_batch_get_nontemporal": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "ddf_batch_autotune": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_float), _vp]),
     "ddf_batch_set_graph": (C.c_int, [_vp, C.c_int32]),

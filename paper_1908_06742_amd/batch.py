@@ -92,7 +92,18 @@ class Batch:
         bx, bpc, ms = C.c_int32(), C.c_int32(), C.c_float()
         L.check(L.lib().ddf_batch_autotune(self._h, int(steps_per_trial), C.byref(bx), C.byref(bpc), C.byref(ms),
                                            _stream_ptr(self.stream)))
-        return {"bx_max": bx.value, "blocks_per_cu": bpc.value, "ms_per_step": ms.value}
+        return {"bx_max": bx.value, "blocks_per_cu": bpc.value, "nontemporal": list(self.nontemporal),
+                "ms_per_step": ms.value}
+
+    def set_nontemporal(self, even, odd):
+        """Non-temporal loads and stores in the even / odd step kernel; results do not change."""
+        L.check(L.lib().ddf_batch_set_nontemporal(self._h, int(bool(even)), int(bool(odd))))
+
+    @property
+    def nontemporal(self):
+        e, o = C.c_int32(), C.c_int32()
+        L.check(L.lib().ddf_batch_get_nontemporal(self._h, C.byref(e), C.byref(o)))
+        return int(e.value), int(o.value)
 
     def set_tiling(self, bx_max, blocks_per_cu):
         L.check(L.lib().ddf_batch_set_tiling(self._h, int(bx_max), int(blocks_per_cu)))

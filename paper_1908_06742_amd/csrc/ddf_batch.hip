@@ -61,7 +61,7 @@ struct TileRef {
     int tile;   // tile index inside the instance
 };
 
-template <class S, int SCALAR, bool ODD>
+template <class S, int SCALAR, bool ODD, bool NT>
 __global__ __launch_bounds__(kThreads) void k_batch_step(S *__restrict__ f, S *__restrict__ g,
                                                          const InstDesc<typename Codec<S>::R> *__restrict__ inst,
                                                          const TileRef *__restrict__ tiles, const int ntiles,
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(S *__restrict__ f, S *_
         const auto &D = inst[tr.inst];
         int x, y;
         if (inst_node(D, tr.tile, x, y))
-            step_node<S, SCALAR, true, true, ODD, false, LY_ROW>(f + D.off, g + D.off, D.L, D.P, x, y, t);
+            step_node<S, SCALAR, true, true, ODD, false, LY_ROW, NT>(f + D.off, g + D.off, D.L, D.P, x, y, t);
         else if (D.bx_shift >= 6 && pad_slot<S>(D.L, x, y))   // rectangular tiles: x, y were set
             fill_pad(f + D.off, g + D.off, D.L, x, y);
     }
@@ -111,9 +111,10 @@ struct TuneKey {
     }
 };
 
-std::map<TuneKey, std::pair<int, int>> &tune_cache()
+// tuned (bx_max, blocks_per_cu, non-temporal even, non-temporal odd)
+std::map<TuneKey, std::array<int, 4>> &tune_cache()
 {
-    static std::map<TuneKey, std::pair<int, int>> c;
+    static std::map<TuneKey, std::array<int, 4>> c;
     return c;
 }
 
@@ -150,6 +151,7 @@ struct ddf_batch {
     std::vector<unsigned char> active;   // instances whose tiles are in the step list
     // tiling
     int bx_max, bpc, ntiles, grid;
+    int nt[2];             // non-temporal loads and stores in the even / odd step kernel
     std::vector<int> first, count;
     int num_cu;
     // state
@@ -309,12 +311,12 @@ void launch_batch_step(ddf_batch *b, hipStream_t st, bool odd, int64_t t)
     using R = typename Codec<S>::R;
     const auto *inst = (const InstDesc<R> *)b->d_inst;
     if (b->nstep_tiles == 0) return;
-    if (odd)
-        hipLaunchKernelGGL((k_batch_step<S, SC, true>), dim3(b->grid), dim3(kThreads), 0, st, (S *)b->f, (S *)b->g,
-                           inst, b->d_step_tiles, b->nstep_tiles, t);
-    else
-        hipLaunchKernelGGL((k_batch_step<S, SC, false>), dim3(b->grid), dim3(kThreads), 0, st, (S *)b->f, (S *)b->g,
-                           inst, b->d_step_tiles, b->nstep_tiles, t);
+#define DDF_BS(O_, N_)                                                                                              \
+    hipLaunchKernelGGL((k_batch_step<S, SC, O_, N_>), dim3(b->grid), dim3(kThreads), 0, st, (S *)b->f, (S *)b->g, inst, \
+                       b->d_step_tiles, b->nstep_tiles, t)
+    if (odd) { if (b->nt[1]) DDF_BS(true, true); else DDF_BS(true, false); }
+    else { if (b->nt[0]) DDF_BS(false, true); else DDF_BS(false, false); }
+#undef DDF_BS
 }
 
 void launch_one_step(ddf_batch *b, hipStream_t st, int64_t step)
@@ -482,6 +484,7 @@ int ddf_batch_create(int32_t n, const ddf_params *ps, void *pop_f, void *pop_g, 
     b->snap_valid = false;
     b->initialised = false;
     b->captured_steps = 0;
+    b->nt[0] = b->nt[1] = 0;
     // kernels take the time index as an argument, which a captured graph freezes: a
     // time-dependent force or stochastic rounding keys need eager launches
     b->graph_steps = (b->pulsatile || b->storage == DDF_BF16_SR) ? 0 : 100;
@@ -597,6 +600,28 @@ int ddf_batch_set_tiling(ddf_batch *b, int32_t bx_max, int32_t blocks_per_cu)
     return apply_tiling(b, bx_max, blocks_per_cu, b->cap_stream);
 }
 
+int ddf_batch_set_nontemporal(ddf_batch *b, int32_t even, int32_t odd)
+{
+    if (!b) return fail(DDF_ERR_ARG, "batch is NULL");
+    if ((even != 0 && even != 1) || (odd != 0 && odd != 1)) return fail(DDF_ERR_ARG, "non-temporal flags are 0 or 1");
+    if (b->captured_steps) {
+        int rc = quiesce();
+        if (rc != DDF_OK) return rc;
+    }
+    drop_graph(b);
+    b->nt[0] = even;
+    b->nt[1] = odd;
+    return DDF_OK;
+}
+
+int ddf_batch_get_nontemporal(const ddf_batch *b, int32_t *even, int32_t *odd)
+{
+    if (!b || !even || !odd) return fail(DDF_ERR_ARG, "NULL argument");
+    *even = b->nt[0];
+    *odd = b->nt[1];
+    return DDF_OK;
+}
+
 int ddf_batch_get_tiling(const ddf_batch *b, int32_t *bx_max, int32_t *blocks_per_cu, int32_t *ntiles, int32_t *grid)
 {
     if (!b) return fail(DDF_ERR_ARG, "batch is NULL");
@@ -672,7 +697,9 @@ int ddf_batch_autotune(ddf_batch *b, int32_t steps_per_trial, int32_t *bx_max_ou
         std::lock_guard<std::mutex> lk(tune_mutex());
         auto it = tune_cache().find(key);
         if (it != tune_cache().end()) {
-            int rc = apply_tiling(b, it->second.first, it->second.second, st);
+            b->nt[0] = it->second[2];
+            b->nt[1] = it->second[3];
+            int rc = apply_tiling(b, it->second[0], it->second[1], st);
             if (rc != DDF_OK) return rc;
             if (bx_max_out) *bx_max_out = b->bx_max;
             if (blocks_per_cu_out) *blocks_per_cu_out = b->bpc;
@@ -692,34 +719,52 @@ int ddf_batch_autotune(ddf_batch *b, int32_t steps_per_trial, int32_t *bx_max_ou
     DDF_HIP_TRY(hipEventCreate(&e0));
     DDF_HIP_TRY(hipEventCreate(&e1));
     float best = 1e30f;
-    int best_bx = 512, best_bpc = 0;
-    for (int bx : kBxCandidates) {
+    int best_bx = 512, best_bpc = 0, best_nt[2] = {0, 0};
+    auto trial = [&](int bx, int bpc, int nte, int nto) -> int {
+        b->nt[0] = nte;
+        b->nt[1] = nto;
+        int rc = apply_tiling(b, bx, bpc, st);
+        if (rc != DDF_OK) return rc;
+        launch_one_step(b, st, 0);
+        launch_one_step(b, st, 1);
+        (void)hipEventRecord(e0, st);
+        for (int k = 0; k < steps_per_trial; ++k) launch_one_step(b, st, k);
+        (void)hipEventRecord(e1, st);
+        DDF_HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)steps_per_trial;
+        if (ms < best) {
+            best = ms;
+            best_bx = bx;
+            best_bpc = bpc;
+            best_nt[0] = nte;
+            best_nt[1] = nto;
+        }
+        return DDF_OK;
+    };
+    // tile shapes with plain accesses, then non-temporal accesses per parity on the best
+    for (int bx : kBxCandidates)
         for (int bpc : kBpcCandidates) {
-            int rc = apply_tiling(b, bx, bpc, st);
+            int rc = trial(bx, bpc, 0, 0);
             if (rc != DDF_OK) return rc;
-            launch_one_step(b, st, 0);
-            launch_one_step(b, st, 1);
-            (void)hipEventRecord(e0, st);
-            for (int k = 0; k < steps_per_trial; ++k) launch_one_step(b, st, k);
-            (void)hipEventRecord(e1, st);
-            DDF_HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            ms /= (float)steps_per_trial;
-            if (ms < best) {
-                best = ms;
-                best_bx = bx;
-                best_bpc = bpc;
-            }
+        }
+    {
+        const int bx = best_bx, bpc = best_bpc;
+        for (const auto &nt : {std::array<int, 2>{1, 0}, std::array<int, 2>{0, 1}, std::array<int, 2>{1, 1}}) {
+            int rc = trial(bx, bpc, nt[0], nt[1]);
+            if (rc != DDF_OK) return rc;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    b->nt[0] = best_nt[0];
+    b->nt[1] = best_nt[1];
     int rc = apply_tiling(b, best_bx, best_bpc, st);
     if (rc != DDF_OK) return rc;
     {
         std::lock_guard<std::mutex> lk(tune_mutex());
-        tune_cache()[key] = {best_bx, best_bpc};
+        tune_cache()[key] = {best_bx, best_bpc, best_nt[0], best_nt[1]};
     }
     b->initialised = false;
     if (bx_max_out) *bx_max_out = best_bx;

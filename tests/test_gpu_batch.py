@@ -130,17 +130,19 @@ def test_result_independent_of_tiling():
     say("case: batch tilings")
     items = mixed_problems("f32")
     ref = None
-    for bx in (0, 64, 128, 256, 512):     # 0: flat tiles
-        for bpc in (0, 2, 8):
+    for bx, bpc, nt in [(bx, bpc, (0, 0)) for bx in (0, 64, 128, 256, 512) for bpc in (0, 2, 8)] + \
+            [(64, 0, (1, 0)), (64, 0, (0, 1)), (128, 2, (1, 1)), (0, 0, (1, 1))]:     # bx 0: flat tiles
             b = Batch([p for p, _ in items], device=DEV)
             b.set_tiling(bx, bpc)
+            b.set_nontemporal(*nt)
+            assert b.nontemporal == nt
             b.init([f for _, f in items]).step(9)
             pops = [b.get_populations(i, raw=True) for i in range(len(items))]
             if ref is None:
                 ref = pops
             else:
                 for i in range(len(items)):
-                    assert torch.equal(pops[i][0], ref[i][0]) and torch.equal(pops[i][1], ref[i][1]), (bx, bpc, i)
+                    assert torch.equal(pops[i][0], ref[i][0]) and torch.equal(pops[i][1], ref[i][1]), (bx, bpc, nt, i)
 
 
 def test_autotune_then_run():
@@ -155,6 +157,7 @@ def test_autotune_then_run():
     b2 = Batch([p for p, _ in items], device=DEV)
     t2 = b2.autotune(steps_per_trial=4)
     assert (t2["bx_max"], t2["blocks_per_cu"]) == (t["bx_max"], t["blocks_per_cu"]) and t2["ms_per_step"] < 0
+    assert t2["nontemporal"] == t["nontemporal"]
 
 
 def test_per_instance_statistics_and_nonfinite_flag():
