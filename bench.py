@@ -180,8 +180,16 @@ def run_cavity(n=1024, cap=200_000, tol=1e-8):
     ux, uy, phi, wz = e["ux"], e["uy"], e["phi"], e["wz"]
     curl = torch.zeros_like(wz)
     curl[1:-1, 1:-1] = 0.5 * (uy[1:-1, 2:] - uy[1:-1, :-2]) - 0.5 * (ux[2:, 1:-1] - ux[:-2, 1:-1])
-    def err(mask):
-        return float(torch.linalg.norm((wz - curl)[mask]) / torch.linalg.norm(curl[mask]))
+    # the second-order scalar-curvature term the paper's n5 relation drops:
+    # -2 c^2 [(1/w6 - 1/2) + (1/w7 - 1/2)] d_x d_y phi / ((beta1 - beta2) phi), with the
+    # mixed derivative of the extracted phi by centred differences
+    dxy = torch.zeros_like(phi)
+    dxy[1:-1, 1:-1] = 0.25 * (phi[2:, 2:] - phi[2:, :-2] - phi[:-2, 2:] + phi[:-2, :-2])
+    w6, w7 = pr.omega_phi_hi[3], pr.omega_phi_hi[4]
+    pred = -2.0 * pr.cs2phi * ((1.0 / w6 - 0.5) + (1.0 / w7 - 0.5)) * dxy / ((pr.beta1 - pr.beta2) * phi)
+
+    def err(mask, w=wz):
+        return float(torch.linalg.norm((w - curl)[mask]) / torch.linalg.norm(curl[mask]))
 
     m = torch.zeros_like(phi, dtype=torch.bool)
     m[2:-2, 2:-2] = True
@@ -190,11 +198,18 @@ def run_cavity(n=1024, cap=200_000, tol=1e-8):
     c[n // 4:3 * n // 4, n // 4:3 * n // 4] = True
     c &= phi >= 0.1
     ew, ec = err(m), (err(c) if bool(c.any()) else None)
+    ewc = err(m, wz - pred)
+    ecc = err(c, wz - pred) if bool(c.any()) else None
+    # the term alone, against the whole difference
+    share = float(torch.linalg.norm(pred[m]) / torch.linalg.norm((wz - curl)[m]))
     return {"workload": f"lid-driven cavity {n}^2, Re 1000, U 0.1, f32, to r < {tol:g} or {cap} steps",
             "mlups": round(n * n * r["steps"] / dt / 1e6, 1), "steps": r["steps"], "status": r["status"],
             "seconds": round(dt, 3), "res_u": r["res_u"], "res_phi": r["res_phi"],
             "mass_drift_rel": abs(s["mass"] - m0) / m0, "nonfinite": s["nonfinite"],
-            "omega_vs_fd_curl_rel_l2": ew, "omega_vs_fd_curl_rel_l2_centre_quarter": ec}
+            "omega_vs_fd_curl_rel_l2": ew, "omega_vs_fd_curl_rel_l2_centre_quarter": ec,
+            "omega_minus_curvature_term_vs_fd_curl_rel_l2": ewc,
+            "omega_minus_curvature_term_vs_fd_curl_rel_l2_centre_quarter": ecc,
+            "curvature_term_over_difference_l2": share}
 
 
 def stream_ceilings(nbytes=2 << 30, reps=5):
@@ -272,28 +287,43 @@ def run_batch(steps=20000, count=256):
 
 
 def run_surrogate(count=16, cap=400_000):
-    """Time to r < 1e-8 of the `count` lowest-Re held-out 256^2 cavities (seeds
-    100000..100199), FP32: cold from rest in one batch, and warm from the shipped
-    network's prediction (inference and the fallback check inside the timed region);
-    plus the sequential single-lattice estimate (measured per-step time x cold steps)."""
+    """Time to r < 1e-8 of `count` held-out 256^2 cavities spread evenly over the Re
+    range (seeds 100000..100199, every 200/count-th by Re), FP32: cold from rest one
+    lattice at a time (each stepped alone on the GPU with the residual check every 100
+    steps, as run), cold from rest in one batch, and warm from the shipped network's
+    prediction in one batch (inference and the fallback check inside the timed region).
+    Instances that reach the cap count with the cap."""
     import numpy as np
     import torch
 
     import workloads as W
-    from paper_1908_06742_amd import Batch
+    from paper_1908_06742_amd import Batch, Lattice
     from paper_1908_06742_amd import surrogate as S
-    from paper_1908_06742_amd.steady import batch_run_to_steady
-    from paper_1908_06742_amd.surrogate_study import single_step_seconds
+    from paper_1908_06742_amd.steady import batch_run_to_steady, run_to_steady
 
     n = 256
     held = W.surrogate_cases(200, W.SURROGATE_HELDOUT_SEED0)
-    cases = sorted(held, key=lambda c: c[0])[:count]
+    order = sorted(range(len(held)), key=lambda i: held[i][0])
+    cases = [held[order[int(round(q))]] for q in np.linspace(0, len(held) - 1, count)]
     probs = [W.cavity_problem(n, re, u) for re, u in cases]
     re = torch.tensor([c[0] for c in cases], dtype=torch.float32, device="cuda")
     u = torch.tensor([c[1] for c in cases], dtype=torch.float32, device="cuda")
     Batch(probs, device="cuda").autotune(10)
     net, _ = S.load_weights(os.path.join(ROOT, "paper_1908_06742_amd", "weights", "unet_cavity256.npz"))
     S.predict_batch_fields(net, re, u, n, n)       # first call allocates the activations
+    # cold, one lattice at a time
+    single_steps, single_conv = [], 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pr in probs:
+        lat = Lattice(pr, device="cuda").init(*W.cavity_fields(n))
+        r1 = run_to_steady(lat, tol=1e-8, max_steps=cap, check_every=100)
+        single_steps.append(r1["steps"])
+        single_conv += r1["status"] == "converged"
+        del lat
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    # cold, one batch
     b = Batch(probs, device="cuda")
     b.autotune(10)                                  # cached: applies the probe's tiling
     torch.cuda.synchronize()
@@ -304,6 +334,7 @@ def run_surrogate(count=16, cap=400_000):
     torch.cuda.synchronize()
     t_cold = time.perf_counter() - t0
     del b
+    # warm, one batch
     b = Batch(probs, device="cuda")
     b.autotune(10)
     torch.cuda.synchronize()
@@ -314,11 +345,13 @@ def run_surrogate(count=16, cap=400_000):
     t_warm = time.perf_counter() - t0
     sc = np.where(rc["steps_to_converge"] >= 0, rc["steps_to_converge"], cap)
     sw = np.where(rw["steps_to_converge"] >= 0, rw["steps_to_converge"] + 100, cap)
-    t_single = single_step_seconds(cases[0], n, steps=10_000) * float(sc.sum())
-    return {"workload": f"{count} lowest-Re held-out 256^2 cavities, FP32, to r < 1e-8 (cap {cap})",
-            "seconds_cold_single_estimate": round(t_single, 2), "seconds_cold_batch": round(t_cold, 2),
+    return {"workload": f"{count} held-out 256^2 cavities spread over Re {cases[0][0]:.0f}..{cases[-1][0]:.0f}, "
+                        f"FP32, to r < 1e-8 (cap {cap})",
+            "re": [round(c[0], 1) for c in cases],
+            "seconds_cold_single": round(t_single, 2), "seconds_cold_batch": round(t_cold, 2),
             "seconds_warm_batch": round(t_warm, 2), "speedup_vs_cold_single": round(t_single / t_warm, 2),
             "speedup_vs_cold_batch": round(t_cold / t_warm, 2), "fallbacks": int(fb.sum()),
+            "converged_cold_single": int(single_conv),
             "converged_cold": int(np.sum(rc["status"] == "converged")),
             "converged_warm": int(np.sum(rw["status"] == "converged")),
             "steps_cold_over_warm": round(float(sc.sum() / sw.sum()), 2)}

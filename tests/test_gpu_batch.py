@@ -274,13 +274,20 @@ def test_full_size_batch_sampled_instances_match_oracle():
     for k in sorted(picks):
         pr = inst[k].problem.with_(storage="f64")
         _, _, ref = oracle.Oracle(pr, nthreads=8).run(fields[k], 100)
-        out = {n: v.cpu().numpy() for n, v in b.extract(k, ["ux", "uy", "phi"]).items()}
+        out = {n: v.cpu().numpy() for n, v in b.extract(k, ["ux", "uy", "phi", "wz"]).items()}
         # FP32 offset arithmetic against FP64, measured on the instance's own velocity scale
         u_scale = max(np.max(np.abs(ref["ux"])), np.max(np.abs(ref["uy"])))
         eu = max(np.max(np.abs(out["ux"] - ref["ux"])), np.max(np.abs(out["uy"] - ref["uy"]))) / u_scale
         ep = np.max(np.abs(out["phi"] - ref["phi"]))
-        say(f"  instance {k} ({inst[k].kind} {inst[k].nx}x{inst[k].ny}): u {eu:.2e} of max|u| {u_scale:.2e}, phi {ep:.2e}")
+        # omega after the walled trajectory: relative L2 over nodes with phi >= 0.1 (the
+        # error measure of the FP32 storage bar for omega)
+        m = (ref["phi"] >= 0.1) & np.isfinite(ref["wz"])
+        assert np.array_equal(np.isfinite(out["wz"][m]), np.ones(int(m.sum()), bool)), k
+        ew = float(np.linalg.norm((out["wz"] - ref["wz"])[m]) / np.linalg.norm(ref["wz"][m]))
+        say(f"  instance {k} ({inst[k].kind} {inst[k].nx}x{inst[k].ny}): u {eu:.2e} of max|u| {u_scale:.2e}, "
+            f"phi {ep:.2e}, omega {ew:.2e} over {int(m.sum())} nodes")
         assert eu < 1e-5 and ep < 1e-5, k
+        assert int(m.sum()) > 0 and ew < 1e-3, k
 
 
 def test_init_instance_restarts_one_instance_only():

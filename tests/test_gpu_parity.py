@@ -372,6 +372,46 @@ def test_full_size_vortex_field_sampled_nodes():
         assert abs(float(out["wz"][sy, sx]) - ref["wz"][k, k]) < 1e-2 * w_scale, (sx, sy)
 
 
+def test_full_size_fp64_vortex_field_sampled_nodes():
+    # The FP64 path at full size stands in for the oracle in the 8192^2 storage-error
+    # study: 8192^2 periodic vortex field, FP64 storage, the launch settings it runs with
+    # there (x-interleaved rows, one workgroup per CU, 32-bit offsets), checked after 6
+    # and 7 steps (both streaming parities) against the oracle on the (2k+1)^2 periodic
+    # patch each sampled node depends on, at the FP64 bars.
+    L = 8192
+    say("case: 8192^2 f64 sampled nodes")
+    vf = W.VortexField(L=L)
+    pr = W.vortex_problem(L, storage="f64")
+    rho, ux, uy, phi = vf.eval_grid(np.arange(L), np.arange(L), device=DEV)
+    lat = Lattice(pr, device=DEV).init(rho, ux, uy, phi)
+    del rho, ux, uy, phi
+    assert lat.layout == "interleaved" and lat.workgroups_per_cu == (1, 1) and lat.address_width == 32
+    rng = np.random.default_rng(11)
+    samples = [(0, 0), (L - 1, L - 1), (63, 64), (64, 8191)] + [tuple(int(v) for v in rng.integers(0, L, 2))
+                                                                for _ in range(6)]
+    buf = torch.empty((8, L, L), dtype=torch.float64, device=DEV)   # planes rho .. wz
+    names = ["rho", "ux", "uy", "phi", "Sxx", "Syy", "Sxy", "wz"]
+    done = 0
+    for k in (6, 7):
+        lat.step(k - done)
+        done = k
+        out = lat.extract(names, out=buf)
+        got = {n: {(sx, sy): float(out[n][sy, sx]) for sx, sy in samples} for n in names}
+        P = 2 * k + 1
+        for sx, sy in samples:
+            o = oracle.Oracle(W.Problem(nx=P, ny=P, tau=pr.tau, tau_phi=pr.tau_phi))
+            xs = (np.arange(P) + sx - k) % L
+            ys = (np.arange(P) + sy - k) % L
+            fo, go = o.init(*vf.eval_grid(xs, ys))
+            o.step(fo, go, k)
+            ref = o.extract(fo, go, k)
+            for n, scale in (("rho", 1.0), ("ux", 0.02), ("uy", 0.02), ("phi", 1.0)):
+                assert abs(got[n][(sx, sy)] - ref[n][k, k]) < 1e-12 * scale, (k, sx, sy, n)
+            g_scale = 2e-4    # size of the velocity gradients of this field
+            for n in ("Sxx", "Syy", "Sxy", "wz"):
+                assert abs(got[n][(sx, sy)] - ref[n][k, k]) < 1e-10 * g_scale, (k, sx, sy, n)
+
+
 @pytest.mark.parametrize("storage", ["bf16", "bf16sr"])
 def test_bf16_rounding_of_stored_offsets(storage):
     # A uniform rest state rho = rho0 + d stores w_a d in every node of plane a.  Round to
