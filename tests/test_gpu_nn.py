@@ -179,13 +179,13 @@ def test_cast_weights_multi_matches_per_layer_casts():
 
 
 @pytest.mark.parametrize("accumulate", [0, 1])
-@pytest.mark.parametrize("W,Cout", [(64, 32), (128, 32), (64, 64)])   # k_conv3x3<4, 1>; LDS <128, 1>; LDS <64, 2>
+@pytest.mark.parametrize("W,Cout", [(64, 32), (128, 32), (64, 64)])   # k_conv3x3<4, 1>; rows <128, 4>; LDS <64, 2>
 def test_masked_data_gradient_and_pool_adjoint_equal_relu_backward_after(W, Cout, accumulate):
     # masking each contribution (the fused path of the network's backward) gives the bits
     # of the unmasked kernel followed by the ReLU adjoint, when what is accumulated into
     # is already masked
     r = np.random.default_rng(31 + accumulate + W + Cout)
-    B, H, Cin, cs = 2, 8, 64, 96
+    B, H, Cin, cs = 2, 8, (32 if W == 128 else 64), 96     # W 128: the row-streaming kernel
     dyt, _ = bf(r.standard_normal((B, H, W, Cin)))
     wd, _ = bf(0.1 * r.standard_normal((9, Cout, Cin)))
     act, _ = bf(r.standard_normal((B, H, W, cs)))              # mask channels [16, 48) of a wider tensor
@@ -435,6 +435,9 @@ def test_elementwise_kernels_with_unaligned_channel_counts():
     (1, 2, 512, 32, 96, 32, 0, 96, 0, 0),        # 128-pixel segments, 3 channel tiles
     (2, 3, 256, 32, 32, 64, 16, 64, 32, 1),      # 32 -> 32 channels: 256-pixel segments, slices, accumulate
     (1, 2, 512, 32, 32, 32, 0, 32, 0, 0),        # 32 -> 32 channels: 256-pixel segments
+    (1, 8, 128, 32, 32, 32, 0, 32, 0, 0),        # 32 output channels, rows a multiple of 4: row streaming
+    (2, 4, 256, 96, 32, 96, 0, 64, 32, 1),       # row streaming, 3 input chunks, slices, accumulate
+    (1, 12, 128, 128, 32, 160, 16, 32, 0, 0),    # row streaming, 4 input chunks, input slice
 ])
 def test_conv3x3_lds_configs(B, H, W, Cin, Cout, cs_in, co_in, cs_out, co_out, acc):
     r = np.random.default_rng(B + H + W + Cin + Cout)
