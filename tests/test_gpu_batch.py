@@ -273,26 +273,34 @@ def test_full_size_batch_sampled_instances_match_oracle():
              next(k for k, i in enumerate(inst) if i.kind == "channel")}
     for k in sorted(picks):
         pr = inst[k].problem.with_(storage="f64")
-        _, _, ref = oracle.Oracle(pr, nthreads=8).run(fields[k], 100)
+        _, go, ref = oracle.Oracle(pr, nthreads=8).run(fields[k], 100)
         out = {n: v.cpu().numpy() for n, v in b.extract(k, ["ux", "uy", "phi", "wz"]).items()}
         # FP32 offset arithmetic against FP64, measured on the instance's own velocity scale
         u_scale = max(np.max(np.abs(ref["ux"])), np.max(np.abs(ref["uy"])))
         eu = max(np.max(np.abs(out["ux"] - ref["ux"])), np.max(np.abs(out["uy"] - ref["uy"]))) / u_scale
         ep = np.max(np.abs(out["phi"] - ref["phi"]))
-        # omega after the walled trajectory, over nodes with phi >= 0.1, measured on the
-        # instance's nominal vorticity U / L (lid or centre-line speed over the cavity side
-        # or channel height): 100 steps from rest leave a force-driven channel at a few
-        # 1e-5 of U, where FP32 rounding is a large fraction of omega itself
+        # omega after the walled trajectory, over nodes with phi >= 0.1: relative L2 at most
+        # 1e-3 where omega stands clear of what FP32 offsets can resolve.  That floor is the
+        # FP32 quantum of the largest stored scalar offset, 2^-24 max|g - w phi0|, carried
+        # through the relation's division by c^2 (beta1 - beta2) phi with phi >= 0.1; a
+        # force-driven channel 100 steps from rest moves at 1e-5 of its speed, and its
+        # omega is of that order, so there the error is held to the floor instead.
         m = (ref["phi"] >= 0.1) & np.isfinite(ref["wz"])
         assert np.array_equal(np.isfinite(out["wz"][m]), np.ones(int(m.sum()), bool)), k
         dw = (out["wz"] - ref["wz"])[m]
-        w_nom = inst[k].u / (inst[k].nx if inst[k].kind == "cavity" else inst[k].ny)
-        ew_nom = float(np.sqrt(np.mean(dw * dw)) / w_nom)
-        ew = float(np.linalg.norm(dw) / np.linalg.norm(ref["wz"][m]))
+        w_rest = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None] * pr.phi0
+        floor = 2.0 ** -24 * np.max(np.abs(go - w_rest)) / (pr.cs2phi * (pr.beta1 - pr.beta2) * 0.1)
+        rms_ref, rms_err = float(np.sqrt(np.mean(ref["wz"][m] ** 2))), float(np.sqrt(np.mean(dw * dw)))
+        ew = rms_err / rms_ref
         say(f"  instance {k} ({inst[k].kind} {inst[k].nx}x{inst[k].ny}): u {eu:.2e} of max|u| {u_scale:.2e}, "
-            f"phi {ep:.2e}, omega rms {ew_nom:.2e} of U/L, relative L2 {ew:.2e}, over {int(m.sum())} nodes")
+            f"phi {ep:.2e}, omega: relative L2 {ew:.2e}, rms {rms_ref:.2e}, rms error {rms_err:.2e}, "
+            f"FP32 floor {floor:.2e}, over {int(m.sum())} nodes")
         assert eu < 1e-5 and ep < 1e-5, k
-        assert int(m.sum()) > 0 and ew_nom < 1e-3, k
+        assert int(m.sum()) > 0
+        if rms_ref > 100.0 * floor:
+            assert ew < 1e-3, k
+        else:
+            assert rms_err < floor, k
 
 
 def test_init_instance_restarts_one_instance_only():
