@@ -88,14 +88,16 @@ __global__ __launch_bounds__(64 * WM * WN) void k_conv3x3(const __bf16 *__restri
 
 // Row-streaming convolution for 32 output channels (same contract as k_conv3x3).  A
 // workgroup of four wavefronts computes R consecutive output rows of PB consecutive
-// pixels.  Per 32-channel input chunk it stages the weights of all nine taps into LDS
-// once and then streams the R + 2 input rows those outputs read through a double-buffered
-// LDS row (one pixel of halo on each side): each staged row feeds every output row it
-// touches (up to three), so an input row is staged once per workgroup and chunk instead
-// of three times, and each stage feeds 3 x 2 MFMAs per kernel row and owned tile.  The
-// next row's 16-byte global loads are in flight during the current row's MFMAs.
-// Wavefront w owns pixel tiles w, w + 4, ... of every output row.  Needs Cin % 32 == 0,
-// Cout == 32 per workgroup column (grid.y = Cout / 32), W % PB == 0 and H % R == 0.
+// pixels against one 32-channel output tile.  Per 32-channel input chunk every wavefront
+// holds the MFMA B operands of all nine taps in registers (the 32 x 32 weight tile of
+// each tap, 16-byte loads straight from global memory; every workgroup reads the same
+// 18 KB), and the R + 2 input rows the outputs read stream through a double-buffered
+// LDS row (one pixel of halo on each side).  Each staged row feeds every output row it
+// touches: one LDS read of an A operand (a pixel tile at one kernel column and channel
+// half) feeds up to three MFMAs, one per kernel row, so LDS carries a third of an A
+// operand and no B operand per MFMA.  The next row's 16-byte global loads are in flight
+// during the current row's MFMAs.  Wavefront w owns pixel tiles w, w + 4, ... of every
+// output row.  Needs Cin % 32 == 0, W % PB == 0 and H % R == 0; grid.y = Cout / 32.
 template <int PB, int R>
 __global__ __launch_bounds__(256) void k_conv3x3_rows(const __bf16 *__restrict__ in, int N, int H, int W, int Cin,
                                                       int in_cs, int in_co, const __bf16 *__restrict__ wt,
@@ -108,7 +110,6 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(const __bf16 *__restrict__
     static_assert(TW >= 1 && PMT == 4 * TW, "four wavefronts share the pixel tiles evenly");
     constexpr int RS = 40;                       // LDS row stride (32 channels + 8 of padding)
     __shared__ __attribute__((aligned(16))) __bf16 xs[2][PB + 2][RS];
-    __shared__ __attribute__((aligned(16))) __bf16 ws[9][32][RS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = lane & 31, half = lane >> 5;
     const int segs = W / PB, bands = H / R;
@@ -125,8 +126,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(const __bf16 *__restrict__
 #pragma unroll
             for (int j = 0; j < 16; ++j) acc[r][t][j] = 0.0f;
     constexpr int XV = (PB + 2) * 4;             // 16-byte input vectors per staged row
-    constexpr int WV = 9 * 32 * 4;               // 16-byte weight vectors per chunk
-    constexpr int NXV = (XV + 255) / 256, NWV = (WV + 255) / 256;
+    constexpr int NXV = (XV + 255) / 256;
     bf16x8 xr[NXV];
     auto fetch_row = [&](int yi, int c0) {
         const bool row_ok = yi >= 0 && yi < H;
@@ -160,24 +160,16 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(const __bf16 *__restrict__
     const int nc = Cin / 32;
     for (int c = 0; c < nc; ++c) {
         const int c0 = 32 * c;
-        {
-            bf16x8 wr[NWV];
+        // B operands of the chunk: lane (m, half) holds output channel co0 + m, input
+        // channels c0 + 16 k + 8 half .. + 7, for every tap and k
+        bf16x8 bw[9][2];
 #pragma unroll
-            for (int i = 0; i < NWV; ++i) {
-                const int v = tid + 256 * i;
-                const int c8 = v & 3, q = v >> 2, co = q & 31, tap = q >> 5;
-                wr[i] = zero8();
-                if (v < WV) wr[i] = load8(wt + ((int64_t)tap * Cout + co0 + co) * Cin + c0 + 8 * c8);
-            }
-            fetch_row(y0 - 1, c0);
-            __syncthreads();                     // the previous chunk's readers are done
+        for (int tap = 0; tap < 9; ++tap)
 #pragma unroll
-            for (int i = 0; i < NWV; ++i) {
-                const int v = tid + 256 * i;
-                const int q = v >> 2;
-                if (v < WV) *(bf16x8 *)&ws[q >> 5][q & 31][8 * (v & 3)] = wr[i];
-            }
-        }
+            for (int k = 0; k < 2; ++k)
+                bw[tap][k] = load8(wt + ((int64_t)tap * Cout + co0 + m) * Cin + c0 + 16 * k + 8 * half);
+        fetch_row(y0 - 1, c0);
+        if (c > 0) __syncthreads();              // the previous chunk's readers of xs are done
 #pragma unroll
         for (int j = 0; j < R + 2; ++j) {        // input row y0 - 1 + j
             const int b = j & 1;
@@ -189,21 +181,20 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(const __bf16 *__restrict__
             __syncthreads();
             if (j + 1 < R + 2) fetch_row(y0 + j, c0);
 #pragma unroll
-            for (int dy = 0; dy < 3; ++dy) {
-                const int yo = j - dy;           // the output row this input row meets with kernel row dy
-                if (yo < 0 || yo >= R) continue;
+            for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
-                for (int dx = 0; dx < 3; ++dx)
+                for (int k = 0; k < 2; ++k)
 #pragma unroll
-                    for (int k = 0; k < 2; ++k)
+                    for (int t = 0; t < TW; ++t) {
+                        const int pm = wave + 4 * t;
+                        const bf16x8 a = *(const bf16x8 *)&xs[b][32 * pm + m + dx][16 * k + 8 * half];
 #pragma unroll
-                        for (int t = 0; t < TW; ++t) {
-                            const int pm = wave + 4 * t;
-                            const bf16x8 a = *(const bf16x8 *)&xs[b][32 * pm + m + dx][16 * k + 8 * half];
-                            const bf16x8 bw = *(const bf16x8 *)&ws[3 * dy + dx][m][16 * k + 8 * half];
-                            acc[yo][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw, acc[yo][t], 0, 0, 0);
+                        for (int dy = 0; dy < 3; ++dy) {
+                            const int yo = j - dy;   // the output row this input row meets with kernel row dy
+                            if (yo < 0 || yo >= R) continue;
+                            acc[yo][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw[3 * dy + dx][k], acc[yo][t], 0, 0, 0);
                         }
-            }
+                    }
         }
     }
     const int co = co0 + m;
@@ -1040,11 +1031,15 @@ int ddf_nn_conv3x3(const void *in, int32_t N, int32_t H, int32_t W, int32_t Cin,
 #ifndef DDF_CONV_ROWS
 #define DDF_CONV_ROWS 4
 #endif
+#ifndef DDF_CONV_ROWS_COUT
+#define DDF_CONV_ROWS_COUT 96   // also the level-0 decoder's data gradient (32 -> 96 channels): 7% faster
+#endif
 #if DDF_CONV_ROWS > 0
     // measured on 8 x 256^2 against the LDS-staged kernel: 4% faster with 32 input
-    // channels (bit for bit the same sums), 6% with 96, 10% slower with 64
-    if (lds && Cout == 32 && W % 128 == 0 && H % DDF_CONV_ROWS == 0 && Cin != 64) {
-        hipLaunchKernelGGL((k_conv3x3_rows<128, DDF_CONV_ROWS>), dim3((unsigned)(npix / (128 * DDF_CONV_ROWS)), 1u),
+    // channels (bit for bit the same sums), 15% with 96, level with 128; slower with 64
+    // (10%, before the B operands moved to registers)
+    if (lds && (Cout == 32 || Cout == DDF_CONV_ROWS_COUT) && W % 128 == 0 && H % DDF_CONV_ROWS == 0 && Cin != 64) {
+        hipLaunchKernelGGL((k_conv3x3_rows<128, DDF_CONV_ROWS>), dim3((unsigned)(npix / (128 * DDF_CONV_ROWS)), (unsigned)(Cout / 32)),
                            dim3(256), 0, st, i, N, H, W, Cin, in_cs, in_co, w, bias, o, Cout, out_cs, out_co, relu,
                            accumulate, mk, mask_cs, mask_co);
         return check_launch();
