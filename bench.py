@@ -261,7 +261,8 @@ def stream_ceilings(nbytes=2 << 30, reps=5):
 
 def run_batch(steps=20000, count=256):
     """256 cavities and channels of sides 64..512, Re 100..5000, U 0.05..0.1 (seeded),
-    FP32, autotuned tiling, graph-captured runs of 100 steps."""
+    FP32 in packed rows, autotuned tiling and cache policy, graph-captured runs of 100
+    steps."""
     import numpy as np
     import torch
 
@@ -281,7 +282,8 @@ def run_batch(steps=20000, count=256):
     dt = time.perf_counter() - t0
     nodes = b.total_nodes
     return {"instances": count, "nodes": nodes, "mlups": round(nodes * steps / dt / 1e6, 1), "steps": steps,
-            "seconds": round(dt, 3), "tiling": b.tiling(), "autotune_ms_per_step": tune["ms_per_step"],
+            "seconds": round(dt, 3), "tiling": b.tiling(), "nontemporal": list(b.nontemporal),
+            "autotune_ms_per_step": tune["ms_per_step"],
             "nonfinite_instances": int(np.sum(s["nonfinite"] > 0)),
             "hbm_gbs": round(144.0 * nodes * steps / dt / 1e9, 1)}
 

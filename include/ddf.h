@@ -80,19 +80,24 @@ enum {
     DDF_NUM_OUTPUTS
 };
 
-/* Row layout of the population planes of a single lattice.  Row-major: node x of a row
- * at column x.  x-interleaved: the row is 64 sub-rows of Q = nx / 64 nodes, node x at
- * column (x mod 64) Q + x / 64, so the 64 nodes of a wavefront are consecutive in
- * memory and their x +- 1 neighbours sit at the same lanes of the adjacent sub-row
- * (whole aligned cache lines in both streaming parities; the step kernels then load and
- * store non-temporally).  It needs nx = 64 * 2^k with nx / 64 at least one 128-byte line
- * of the storage type (nx >= 1024 in F64, 2048 in F32, 4096 in 16-bit storage).  AUTO
- * takes it for such lattices whose two population arrays exceed 256 MB (they stream from
- * HBM), else row-major.  The layout is internal: every entry point reads and writes
- * fields and populations in the logical [ny][nx] order either way, and results are the
- * same bit for bit (reduction sums up to their summation order).  Batches are row-major
- * (DDF_ERR_UNSUPPORTED for INTERLEAVED). */
-enum { DDF_LAYOUT_AUTO = 0, DDF_LAYOUT_ROW = 1, DDF_LAYOUT_INTERLEAVED = 2 };
+/* Row layout of the population planes.  Row-major: node x of a row at column x, rows
+ * padded to a multiple of 64 elements.  x-interleaved: the row is 64 sub-rows of
+ * Q = nx / 64 nodes, node x at column (x mod 64) Q + x / 64, so the 64 nodes of a
+ * wavefront are consecutive in memory and their x +- 1 neighbours sit at the same lanes
+ * of the adjacent sub-row (whole aligned cache lines in both streaming parities; the step
+ * kernels then load and store non-temporally).  It needs nx = 64 * 2^k with nx / 64 at
+ * least one 128-byte line of the storage type (nx >= 1024 in F64, 2048 in F32, 4096 in
+ * 16-bit storage).  Packed: row-major rows of exactly nx elements with no padding, each
+ * direction plane rounded up to 64 elements (so that planes start on a 128-byte line).
+ * For a single lattice AUTO takes x-interleaved rows where the width allows them and the
+ * two population arrays exceed 256 MB (they stream from HBM), else row-major; packed
+ * rows only on request.  Batches always keep packed rows (AUTO or PACKED;
+ * DDF_ERR_UNSUPPORTED for ROW and INTERLEAVED), which their flat tiles stream as whole
+ * lines.  The layout is internal: every entry point reads and writes fields and
+ * populations in the logical [ny][nx] order, and results are the same bit for bit in
+ * every layout (stochastic rounding included; reduction sums up to their summation
+ * order). */
+enum { DDF_LAYOUT_AUTO = 0, DDF_LAYOUT_ROW = 1, DDF_LAYOUT_INTERLEAVED = 2, DDF_LAYOUT_PACKED = 3 };
 
 /* Statistics returned by ddf_reduce (all from one FP64 pass over the state). */
 enum {
@@ -132,11 +137,12 @@ typedef struct {
 
 typedef struct ddf_handle ddf_handle;
 
-/* Row pitch in elements of every population plane (a multiple of 64). */
+/* Row pitch in elements of every population plane: nx rounded up to 64, or nx for
+ * DDF_LAYOUT_PACKED. */
 int64_t ddf_pitch(const ddf_params *p);
-/* Elements from one direction plane to the next: pitch * ny, plus a 256 KiB + 256 B
- * gap for planes of 16 MiB or more (it spreads the 18 concurrent streams over the
- * HBM channel interleave). */
+/* Elements from one direction plane to the next: pitch * ny rounded up to 64, plus a
+ * 256 KiB + 256 B gap for planes of 16 MiB or more (it spreads the 18 concurrent
+ * streams over the HBM channel interleave). */
 int64_t ddf_plane_stride(const ddf_params *p);
 /* Bytes of one lattice's populations: 9 planes of ddf_plane_stride storage elements.
  * The caller allocates two such buffers (f and g). */
@@ -220,7 +226,7 @@ int ddf_get_workgroups_per_cu(const ddf_handle *h, int32_t *even, int32_t *odd);
  * (after waiting for the device). */
 int ddf_set_graph(ddf_handle *h, int32_t steps_per_graph);
 
-/* DDF_LAYOUT_ROW or DDF_LAYOUT_INTERLEAVED: the layout ddf_create chose. */
+/* DDF_LAYOUT_ROW, DDF_LAYOUT_INTERLEAVED or DDF_LAYOUT_PACKED: the layout ddf_create chose. */
 int32_t ddf_get_layout(const ddf_handle *h);
 
 int64_t ddf_step_count(const ddf_handle *h);
@@ -229,8 +235,9 @@ const char *ddf_last_error(void);
 /* ---------------------------------------------------------------------------------
  * Batches: n independent lattices (own size, rates, walls, force) advanced together
  * by one persistent launch per time step.  All instances share one storage type and
- * one scalar collision model.  Instance i's populations sit at a 256-byte aligned
- * offset of one f and one g buffer (ddf_batch_offsets); its dense fields sit at a
+ * one scalar collision model.  Instance i's populations (packed rows, DDF_LAYOUT_PACKED)
+ * sit at a 256-byte aligned offset of one f and one g buffer (ddf_batch_offsets):
+ * ddf_population_bytes of its parameters with layout PACKED; its dense fields sit at a
  * node offset of concatenated [ny_i][nx_i] arrays.  Runs of K steps (default 100,
  * ddf_batch_set_graph) are captured once into a hipGraph on an internal stream and
  * replayed on the caller's stream; batches with a time-dependent force step eagerly.
@@ -260,9 +267,10 @@ int ddf_batch_init_equilibrium(ddf_batch *b, const double *rho, const double *ux
                                const double *phi, void *stream);
 /* Tiling: tile width at most bx_max (64, 128, 256 or 512; 512 threads per tile), or
  * bx_max = 0 for flat tiles of 512 consecutive nodes in row-major order (instances whose
- * sides are not multiples of a tile then leave idle lanes only in their last tile); and
- * blocks_per_cu persistent workgroups per compute unit (0 = one workgroup per tile).
- * Results do not depend on the tiling.  Invalidates the captured graph. */
+ * sides are not multiples of a tile then leave idle lanes only in their last tile; the
+ * default at creation); and blocks_per_cu persistent workgroups per compute unit (0 =
+ * one workgroup per tile).  Results do not depend on the tiling.  Invalidates the
+ * captured graph. */
 int ddf_batch_set_tiling(ddf_batch *b, int32_t bx_max, int32_t blocks_per_cu);
 int ddf_batch_get_tiling(const ddf_batch *b, int32_t *bx_max, int32_t *blocks_per_cu, int32_t *ntiles, int32_t *grid);
 /* Non-temporal (streaming) loads and stores in the even and in the odd step kernel (0 or

@@ -21,8 +21,8 @@ STATUS_NAMES = {0: "DDF_OK", -1: "DDF_ERR_ARG", -2: "DDF_ERR_UNSUPPORTED", -3: "
                 -4: "DDF_ERR_NONFINITE", -5: "DDF_ERR_STATE"}
 
 FORCE = {"none": 0, "uniform": 1, "fourroll": 2, "pulsatile": 3}
-LAYOUT = {"auto": 0, "row": 1, "interleaved": 2}
-LAYOUT_NAMES = {1: "row", 2: "interleaved"}
+LAYOUT = {"auto": 0, "row": 1, "interleaved": 2, "packed": 3}
+LAYOUT_NAMES = {1: "row", 2: "interleaved", 3: "packed"}
 SCALAR = {"mrt": 0, "srt": 1, "cascaded": 2, "central": 3}
 
 OUTPUTS = ("rho", "ux", "uy", "phi", "Sxx", "Syy", "Sxy", "wz",

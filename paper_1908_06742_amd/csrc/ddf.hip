@@ -167,7 +167,8 @@ int ddf_create(const ddf_params *p, void *pop_f, void *pop_g, void *workspace, d
     if (p->layout == DDF_LAYOUT_INTERLEAVED && qs == 0)
         return fail(DDF_ERR_UNSUPPORTED, "x-interleaved rows need nx = 64 * 2^k with nx / 64 >= one 128-byte line "
                                          "of the storage type");
-    if (p->layout == DDF_LAYOUT_ROW || (p->layout == DDF_LAYOUT_AUTO && 2 * population_bytes(p) <= (size_t)256 << 20))
+    if (p->layout == DDF_LAYOUT_ROW || p->layout == DDF_LAYOUT_PACKED ||
+        (p->layout == DDF_LAYOUT_AUTO && 2 * population_bytes(p) <= (size_t)256 << 20))
         qs = 0;
     ddf_handle *h = new (std::nothrow) ddf_handle;
     if (!h) return fail(DDF_ERR_ARG, "out of host memory");
@@ -218,7 +219,12 @@ int ddf_set_graph(ddf_handle *h, int32_t steps_per_graph)
 
 int32_t ddf_get_tile_width(const ddf_handle *h) { return h ? h->tile_width : 0; }
 
-int32_t ddf_get_layout(const ddf_handle *h) { return !h ? 0 : (h->G.L.qs ? DDF_LAYOUT_INTERLEAVED : DDF_LAYOUT_ROW); }
+int32_t ddf_get_layout(const ddf_handle *h)
+{
+    if (!h) return 0;
+    if (h->G.L.qs) return DDF_LAYOUT_INTERLEAVED;
+    return h->p.layout == DDF_LAYOUT_PACKED ? DDF_LAYOUT_PACKED : DDF_LAYOUT_ROW;
+}
 
 int64_t ddf_step_count(const ddf_handle *h) { return h ? h->step : -1; }
 

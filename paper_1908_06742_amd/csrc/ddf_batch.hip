@@ -1,8 +1,9 @@
 // libddf, batched entry points: many independent lattices of uneven size and
 // parameters advanced by one persistent launch per time step.
 //
-// Every instance keeps its own population planes (layout of ddf_kernels.hpp) at a
-// 256-byte aligned offset inside one f and one g buffer.  The tiles of all instances
+// Every instance keeps its own population planes in packed rows (rows of exactly nx
+// nodes, planes rounded up to 64 elements; ddf_kernels.hpp) at a 256-byte aligned
+// offset inside one f and one g buffer.  The tiles of all instances
 // form one flat list; a fixed grid of workgroups walks it, each XCD taking one
 // contiguous run of tiles (instances are laid out one after the other, so an XCD's
 // L2 sees whole neighbourhoods).  Tile width and workgroups per CU are chosen by
@@ -76,8 +77,6 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(S *__restrict__ f, S *_
         int x, y;
         if (inst_node(D, tr.tile, x, y))
             step_node<S, SCALAR, true, true, ODD, false, LY_ROW, NT>(f + D.off, g + D.off, D.L, D.P, x, y, t);
-        else if (D.bx_shift >= 6 && pad_slot<S>(D.L, x, y))   // rectangular tiles: x, y were set
-            fill_pad(f + D.off, g + D.off, D.L, x, y);
     }
 }
 
@@ -206,6 +205,13 @@ int max_tiles_of(int n, const ddf_params *ps)
     return best;
 }
 
+// Batch instances always keep packed rows.
+ddf_params packed(ddf_params p)
+{
+    p.layout = DDF_LAYOUT_PACKED;
+    return p;
+}
+
 int validate_batch(int n, const ddf_params *ps)
 {
     if (n <= 0 || !ps) return fail(DDF_ERR_ARG, "batch needs n > 0 instances");
@@ -216,8 +222,9 @@ int validate_batch(int n, const ddf_params *ps)
         const int m0 = ps[0].scalar_model == DDF_SCALAR_CASCADED ? DDF_SCALAR_CENTRAL : ps[0].scalar_model;
         const int mi = ps[i].scalar_model == DDF_SCALAR_CASCADED ? DDF_SCALAR_CENTRAL : ps[i].scalar_model;
         if (mi != m0) return fail(DDF_ERR_ARG, "all batch instances must share one scalar collision model");
-        if (ps[i].layout == DDF_LAYOUT_INTERLEAVED)
-            return fail(DDF_ERR_UNSUPPORTED, "instance " + std::to_string(i) + ": batches keep row-major rows");
+        if (ps[i].layout == DDF_LAYOUT_ROW || ps[i].layout == DDF_LAYOUT_INTERLEAVED)
+            return fail(DDF_ERR_UNSUPPORTED, "instance " + std::to_string(i) + ": batches keep packed rows "
+                                             "(layout AUTO or PACKED)");
     }
     return DDF_OK;
 }
@@ -423,7 +430,10 @@ size_t ddf_batch_population_bytes(int32_t n, const ddf_params *ps)
 {
     if (n <= 0 || !ps) return 0;
     size_t tot = 0;
-    for (int i = 0; i < n; ++i) tot += population_bytes(&ps[i]);
+    for (int i = 0; i < n; ++i) {
+        const ddf_params q = packed(ps[i]);
+        tot += population_bytes(&q);
+    }
     return tot;
 }
 
@@ -447,6 +457,7 @@ int ddf_batch_create(int32_t n, const ddf_params *ps, void *pop_f, void *pop_g, 
     if (!b) return fail(DDF_ERR_ARG, "out of host memory");
     b->n = n;
     b->p.assign(ps, ps + n);
+    for (ddf_params &q : b->p) q = packed(q);
     b->storage = ps[0].storage;
     b->scalar_model = ps[0].scalar_model;
     b->pulsatile = false;
@@ -455,7 +466,7 @@ int ddf_batch_create(int32_t n, const ddf_params *ps, void *pop_f, void *pop_g, 
     for (int i = 0; i < n; ++i) {
         b->off.push_back(off);
         b->node_off.push_back(nodes);
-        off += (int64_t)(population_bytes(&ps[i]) / s);
+        off += (int64_t)(population_bytes(&b->p[i]) / s);
         nodes += (int64_t)ps[i].nx * ps[i].ny;
         PhysPair pp;
         pp.d = make_phys<double>(ps[i]);
@@ -500,7 +511,7 @@ int ddf_batch_create(int32_t n, const ddf_params *ps, void *pop_f, void *pop_g, 
         return fail(DDF_ERR_HIP, "cannot create the capture stream");
     }
     rc = quiesce();
-    if (rc == DDF_OK) rc = apply_tiling(b, 512, 0, b->cap_stream);
+    if (rc == DDF_OK) rc = apply_tiling(b, 0, 0, b->cap_stream);
     if (rc != DDF_OK) {
         (void)hipStreamDestroy(b->cap_stream);
         delete b;

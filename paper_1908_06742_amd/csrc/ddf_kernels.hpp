@@ -8,6 +8,12 @@
 // node touches at one (x, y) do not start at the same offset of the HBM channel
 // interleave (measured: +2% on 8192^2 FP32).
 //
+// Packed rows (the batch's layout) drop the row padding: pitch = nx, and each plane is
+// rounded up to 64 elements so that every plane starts on a 128-byte line.  Flat tiles
+// of consecutive nodes then read and write whole aligned lines in the even step, and
+// no row ends inside a partly used line (a 256-instance batch of random widths: 5.3
+// against 4.8 TB/s for padded rows).
+//
 // Large lattices whose width is 64 * 2^k (k >= 5 for 4-byte storage) may instead keep
 // each row x-interleaved: memory column m of a row holds node x = (m mod Q) * 64 + m / Q
 // with Q = nx / 64, i.e. the row is 64 sub-rows of Q nodes, 64 apart in x.  A wavefront
@@ -50,6 +56,8 @@ struct Lat {
     int64_t plane;      // elements per direction plane
     int px, py;         // periodic flags
     int qs;             // x-interleaved rows: log2(nx / 64); 0 = row-major
+    int kpitch;         // pitch and plane of padded row-major rows: the stochastic-rounding
+    int64_t kplane;     // keys name slots by these, so every layout draws the same bits
 };
 
 // Row layouts, as template arguments: row-major, x-interleaved, or read from Lat::qs.
@@ -185,6 +193,15 @@ __device__ __forceinline__ int64_t logical_slot(const Lat &L, int x, int y, int 
     return (int64_t)pa * L.plane + cell;
 }
 
+// The lattice as padded row-major rows (slot indices that name stochastic-rounding keys).
+__device__ __forceinline__ Lat key_lat(Lat L)
+{
+    L.pitch = L.kpitch;
+    L.plane = L.kplane;
+    L.qs = 0;
+    return L;
+}
+
 // Element `cell` of direction plane `pa`.  With IDX32 (planes below 4 GiB) the lane's
 // part of the address is a 32-bit byte offset from the plane's base; where the plane
 // is the same for the whole wavefront (every slot of a periodic lattice) that base
@@ -267,7 +284,7 @@ __device__ __forceinline__ void step_node(S *__restrict__ f, S *__restrict__ g, 
     // step, the node and the direction, which every step writes exactly once each; the
     // key names the node by its coordinates, so both row layouts store the same bits
     const uint32_t salt = sr_step_salt(t);
-    const int64_t key = 9 * ((int64_t)y * L.pitch + x);
+    const int64_t key = 9 * ((int64_t)y * L.kpitch + x);
     // rest direction: same slot in both parities
     {
         const uint32_t h = sr_bits(key, salt);
@@ -431,13 +448,13 @@ __global__ __launch_bounds__(kThreads) void k_init(S *__restrict__ f, S *__restr
     populations(e, fo);
     scalar_eq(P, M, n);
     populations(n, go);
-    const int64_t node = (int64_t)y * G.L.pitch + x;
+    const int64_t node = (int64_t)y * G.L.kpitch + x;
     const int64_t cell = (int64_t)y * G.L.pitch + col_of<LY_ANY>(G.L, x);
     const uint32_t salt = sr_step_salt(-1);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         const int64_t s = (int64_t)a * G.L.plane + cell;
-        const uint32_t h = sr_bits((int64_t)a * G.L.plane + node, salt);   // same bits in either row layout
+        const uint32_t h = sr_bits((int64_t)a * G.L.kplane + node, salt);   // same bits in every row layout
         f[s] = Codec<S>::enc(fo[a] * P.scale, h);
         g[s] = Codec<S>::enc(go[a] * P.scale, h >> 16);
     }
@@ -586,8 +603,8 @@ __global__ __launch_bounds__(kThreads) void k_set(S *__restrict__ f, S *__restri
         if (dtype == 0) {
             const double vf = ((const double *)fi)[a * N + c] - (double)P.rest_f[a] * (double)P.rho0;
             const double vg = ((const double *)gi)[a * N + c] - (double)P.rest_g[a] * (double)P.phi0;
-            // keyed by the slot's row-major index: the same bits in either row layout
-            const uint32_t h = sr_bits(logical_slot<WALLS, ODD, LY_ROW>(G.L, x, y, a), sr_step_salt(-2));
+            // keyed by the slot's index in padded row-major rows: the same bits in every layout
+            const uint32_t h = sr_bits(logical_slot<WALLS, ODD, LY_ROW>(key_lat(G.L), x, y, a), sr_step_salt(-2));
             f[s] = Codec<S>::enc((R)(vf * (double)P.scale), h);
             g[s] = Codec<S>::enc((R)(vg * (double)P.scale), h >> 16);
         } else {
@@ -621,7 +638,10 @@ inline int fail(int code, const std::string &msg)
             return ::ddf::host::fail(DDF_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_));        \
     } while (0)
 
-inline int64_t pitch_of(const ddf_params *p) { return ((int64_t)p->nx + 63) / 64 * 64; }
+// Row pitch in elements: nx rounded up to 64 (row-major and x-interleaved rows), or nx
+// itself for packed rows.
+inline int64_t row_pitch(int nx) { return ((int64_t)nx + 63) / 64 * 64; }
+inline int64_t pitch_of(const ddf_params *p) { return p->layout == DDF_LAYOUT_PACKED ? p->nx : row_pitch(p->nx); }
 
 inline size_t storage_size(int storage) { return storage == DDF_F64 ? 8 : (storage == DDF_F32 ? 4 : 2); }
 
@@ -629,13 +649,15 @@ inline size_t storage_size(int storage) { return storage == DDF_F64 ? 8 : (stora
 // tiles for 8- and 4-byte storage, 64-wide for 2-byte storage).
 inline int default_tile_width(int storage) { return storage_size(storage) == 2 ? 64 : 128; }
 
-// Elements per direction plane: pitch * ny, plus 256 KiB + 256 B for planes of 16 MiB or more.
-inline int64_t plane_of(const ddf_params *p)
+// Elements per direction plane: pitch * ny rounded up to 64, plus 256 KiB + 256 B for
+// planes of 16 MiB or more.
+inline int64_t plane_with(const ddf_params *p, int64_t pitch)
 {
     const int64_t s = (int64_t)storage_size(p->storage);
-    const int64_t base = pitch_of(p) * p->ny;
+    const int64_t base = (pitch * p->ny + 63) / 64 * 64;
     return base * s >= (16ll << 20) ? base + ((256ll << 10) + 256) / s : base;
 }
+inline int64_t plane_of(const ddf_params *p) { return plane_with(p, pitch_of(p)); }
 
 inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -734,6 +756,8 @@ inline Lat make_lat(const ddf_params &p)
     L.px = p.periodic_x ? 1 : 0;
     L.py = p.periodic_y ? 1 : 0;
     L.qs = 0;   // row-major; a single lattice may switch to x-interleaved rows (interleave_shift)
+    L.kpitch = (int)row_pitch(p.nx);
+    L.kplane = plane_with(&p, L.kpitch);
     return L;
 }
 
@@ -783,7 +807,7 @@ inline int validate(const ddf_params *p)
     if (!(std::fabs(p->beta1 - p->beta2) > 1e-12)) return fail(DDF_ERR_ARG, "beta1 == beta2: the vorticity relation is singular");
     if (!(p->cs2 > 0.0) || !(p->cs2_phi > 0.0)) return fail(DDF_ERR_ARG, "cs2 and cs2_phi must be positive");
     if (!(p->rho0 > 0.0)) return fail(DDF_ERR_ARG, "rho0 must be positive");
-    if (p->layout < DDF_LAYOUT_AUTO || p->layout > DDF_LAYOUT_INTERLEAVED) return fail(DDF_ERR_ARG, "unknown layout");
+    if (p->layout < DDF_LAYOUT_AUTO || p->layout > DDF_LAYOUT_PACKED) return fail(DDF_ERR_ARG, "unknown layout");
     if (p->pop_scale < 0.0) return fail(DDF_ERR_ARG, "pop_scale must be >= 0");
     if (p->pop_scale > 0.0) {
         int e;

@@ -145,7 +145,7 @@ class Lattice:
 
     @property
     def layout(self):
-        """Row layout of the population planes ("row" or "interleaved"), chosen at creation."""
+        """Row layout of the population planes ("row", "interleaved" or "packed"), chosen at creation."""
         return L.LAYOUT_NAMES[int(L.lib().ddf_get_layout(self._h))]
 
     @property

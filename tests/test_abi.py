@@ -253,8 +253,29 @@ def test_automatic_layout_interleaves_only_lattices_beyond_the_cache():
     assert _create_rc(W.Problem(nx=32768, ny=32832, storage="f32"))[1] == 2   # 64-bit offsets
 
 
-def test_batches_keep_row_major_rows():
-    ps = (L.Params * 1)(L.params_from_problem(W.Problem(nx=2048, ny=4, storage="f32", layout="interleaved")))
+@pytest.mark.parametrize("layout", ["interleaved", "row"])
+def test_batches_keep_packed_rows(layout):
+    ps = (L.Params * 1)(L.params_from_problem(W.Problem(nx=2048, ny=4, storage="f32", layout=layout)))
     h = C.c_void_p()
     rc = L.lib().ddf_batch_create(1, ps, C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20), C.byref(h))
-    assert rc == L.DDF_ERR_UNSUPPORTED and "row-major" in L.lib().ddf_last_error().decode()
+    assert rc == L.DDF_ERR_UNSUPPORTED and "packed rows" in L.lib().ddf_last_error().decode()
+    assert L.lib().ddf_batch_workspace_bytes(1, ps) == 0
+
+
+@pytest.mark.parametrize("storage,s", [("f64", 8), ("f32", 4), ("f16", 2), ("bf16sr", 2)])
+def test_packed_rows_drop_the_row_padding(storage, s):
+    lib = L.lib()
+    for nx, ny in ((77, 5), (131, 37), (64, 3), (2, 2)):
+        row = L.params_from_problem(W.Problem(nx=nx, ny=ny, storage=storage, layout="row"))
+        pk = L.params_from_problem(W.Problem(nx=nx, ny=ny, storage=storage, layout="packed"))
+        assert lib.ddf_pitch(C.byref(row)) == (nx + 63) // 64 * 64
+        assert lib.ddf_pitch(C.byref(pk)) == nx
+        plane = lib.ddf_plane_stride(C.byref(pk))
+        assert plane == (nx * ny + 63) // 64 * 64          # every plane starts on a 128-byte line
+        assert lib.ddf_population_bytes(C.byref(pk)) == (9 * plane * s + 255) // 256 * 256
+        assert _create_rc(W.Problem(nx=nx, ny=ny, storage=storage, layout="packed")) == (L.DDF_OK, 3)
+    # a batch lays its instances out as packed rows, whatever layout AUTO would give alone
+    probs = [W.Problem(nx=77, ny=5, storage=storage), W.Problem(nx=8192, ny=8192, storage=storage)]
+    ps = (L.Params * 2)(*[L.params_from_problem(p) for p in probs])
+    want = sum(lib.ddf_population_bytes(C.byref(L.params_from_problem(p.with_(layout="packed")))) for p in probs)
+    assert lib.ddf_batch_population_bytes(2, ps) == want

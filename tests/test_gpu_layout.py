@@ -1,10 +1,11 @@
 """x-interleaved rows (the layout the library takes for wide lattices that stream from
-HBM) against row-major rows and against the oracle.
+HBM) and packed rows (the batch's layout) against padded row-major rows and against
+the oracle.
 
-The layout only moves populations in memory, so both layouts must give the same bits
-after any number of steps, in every storage format, with walls, moving walls, body
-forces and every scalar model, and extraction must give the same outputs; reductions
-agree up to their summation order."""
+A layout only moves populations in memory, so every layout must give the same bits
+after any number of steps, in every storage format (stochastic rounding included),
+with walls, moving walls, body forces and every scalar model, and extraction must give
+the same outputs; reductions agree up to their summation order."""
 import math
 import sys
 import zlib
@@ -40,8 +41,8 @@ def _fields(nx, ny, seed, u=0.03):
             u * r.standard_normal((ny, nx)), 1.0 + 0.1 * r.standard_normal((ny, nx)))
 
 
-def _case(kind, storage, model):
-    nx = NX[storage]
+def _case(kind, storage, model, nx=None):
+    nx = NX[storage] if nx is None else nx
     if kind == "periodic":
         pr = W.Problem(nx=nx, ny=5, storage=storage, scalar_model=model)
     elif kind == "cavity":
@@ -152,3 +153,74 @@ def test_interleaved_rows_match_the_oracle(kind, steps):
     sc = max(np.max(np.abs(ref[k][m])) for k in ("Sxx", "Syy", "Sxy", "wz"))
     for k in ("Sxx", "Syy", "Sxy", "wz"):
         assert np.max(np.abs(out[k][m] - ref[k][m])) / sc < 1e-10, k
+
+
+def _compare(row, other, storage):
+    fr, gr = row.get_populations(raw=True)
+    fo, go = other.get_populations(raw=True)
+    torch.cuda.synchronize()
+    assert torch.equal(fr.view(torch.int8), fo.view(torch.int8))
+    assert torch.equal(gr.view(torch.int8), go.view(torch.int8))
+    tol = 1e-13 if storage == "f64" else 2e-6
+    for dt in (torch.float64, torch.float32):
+        er, eo = row.extract(dtype=dt), other.extract(dtype=dt)
+        for k in er:
+            a, b = er[k], eo[k]
+            assert torch.equal(torch.isnan(a), torch.isnan(b)), k
+            m = ~torch.isnan(a)
+            grp = next((g for g in GROUPS if k in g), (k,))
+            scale = max(float(er[j][~torch.isnan(er[j])].abs().max()) for j in grp)
+            if scale > 0:
+                assert float((a[m] - b[m]).abs().max()) <= tol * scale, (k, dt)
+    sr, so = row.reduce(), other.reduce()
+    for k in ("mass", "scalar", "umax", "phimin", "nonfinite"):
+        assert abs(sr[k] - so[k]) <= 1e-14 * max(1.0, abs(sr[k])), k
+
+
+# widths that leave rows ending inside a 128-byte line (and one that fills whole lines)
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "bf16sr"])
+@pytest.mark.parametrize("kind,nx", [("periodic", 77), ("cavity", 131), ("channel", 45), ("fourroll", 64)])
+@pytest.mark.parametrize("steps", [1, 2, 5])
+def test_packed_rows_step_bit_for_bit(storage, kind, nx, steps):
+    model = "central" if kind == "channel" else ("srt" if kind == "fourroll" else "mrt")
+    pr, fields = _case(kind, storage, model, nx=nx)
+    say(f"case: packed {kind} {storage} {model} steps={steps} ({pr.nx}x{pr.ny})")
+    row = Lattice(pr.with_(layout="row"), device=DEV)
+    pk = Lattice(pr.with_(layout="packed"), device=DEV)
+    assert row.layout == "row" and pk.layout == "packed"
+    assert pk.pitch == pr.nx and row.pitch % 64 == 0
+    row.init(*fields).step(steps)
+    pk.init(*fields).step(steps)
+    _compare(row, pk, storage)
+
+
+def test_packed_rows_checkpoint_round_trip_and_tiles():
+    # raw populations written by one layout and read back by the other continue the same
+    # run (stochastic rounding: the keys name slots of padded rows in every layout)
+    pr, fields = _case("channel", "bf16sr", "mrt", nx=45)
+    row = Lattice(pr.with_(layout="row"), device=DEV).init(*fields).step(3)
+    f, g = row.get_populations(raw=True)
+    pk = Lattice(pr.with_(layout="packed"), device=DEV).set_populations(f, g, step=3, raw=True)
+    row.step(4)
+    pk.step(4)
+    _compare(row, pk, "bf16sr")
+    pr, fields = _case("cavity", "f32", "mrt", nx=131)
+    ref = Lattice(pr.with_(layout="row"), device=DEV).init(*fields).step(203)
+    fr, _ = ref.get_populations(raw=True)
+    for tile in (64, 128, 256, 512):
+        say(f"case: packed tile {tile}")
+        pk = Lattice(pr.with_(layout="packed"), device=DEV).set_tile_width(tile).init(*fields).step(203)
+        fp, _ = pk.get_populations(raw=True)
+        torch.cuda.synchronize()
+        assert torch.equal(fr.view(torch.int8), fp.view(torch.int8)), tile
+
+
+@pytest.mark.parametrize("steps", [6, 7])
+def test_packed_rows_match_the_oracle(steps):
+    pr, fields = _case("cavity", "f64", "mrt", nx=131)
+    say(f"case: packed oracle steps={steps}")
+    pk = Lattice(pr.with_(layout="packed"), device=DEV).init(*fields).step(steps)
+    f, g = (t.cpu().numpy() for t in pk.get_populations())
+    fo, go, _ = oracle.Oracle(pr, nthreads=8).run(fields, steps)
+    for a, b in ((f, fo), (g, go)):
+        assert np.max(np.abs(a - b)) / np.max(np.abs(b)) < 1e-12

@@ -48,7 +48,7 @@ class Problem:
     storage: str = "f64"            # f64 | f32 | f16 | bf16
     rho0: float = 1.0
     phi0: float = 1.0
-    layout: str = "auto"            # row layout of the population planes: auto | row | interleaved
+    layout: str = "auto"            # row layout of the population planes: auto | row | interleaved | packed
 
     def with_(self, **kw) -> "Problem":
         return replace(self, **kw)
