@@ -86,38 +86,46 @@ __global__ __launch_bounds__(64 * WM * WN) void k_conv3x3(const __bf16 *__restri
     }
 }
 
-// Row-streaming convolution for 32 output channels (same contract as k_conv3x3).  A
-// workgroup of four wavefronts computes R consecutive output rows of PB consecutive
-// pixels against one 32-channel output tile.  Per 32-channel input chunk every wavefront
-// holds the MFMA B operands of all nine taps in registers (the 32 x 32 weight tile of
-// each tap, 16-byte loads straight from global memory; every workgroup reads the same
-// 18 KB), and the R + 2 input rows the outputs read stream through a double-buffered
+// Row-streaming convolution (same contract as k_conv3x3).  A workgroup of four
+// wavefronts computes R consecutive output rows of PB consecutive pixels against WCO
+// tiles of 32 output channels: wavefront w owns output-channel tile w mod WCO and, of
+// every output row, the pixel tiles w / WCO, w / WCO + 4 / WCO, ...  Per 32-channel
+// input chunk every wavefront holds the MFMA B operands of its tile's nine taps in
+// registers (the 32 x 32 weight tile of each tap, 16-byte loads straight from global
+// memory), and the R + 2 input rows the outputs read stream through a double-buffered
 // LDS row (one pixel of halo on each side).  Each staged row feeds every output row it
 // touches: one LDS read of an A operand (a pixel tile at one kernel column and channel
 // half) feeds up to three MFMAs, one per kernel row, so LDS carries a third of an A
-// operand and no B operand per MFMA.  The next row's 16-byte global loads are in flight
-// during the current row's MFMAs.  Wavefront w owns pixel tiles w, w + 4, ... of every
-// output row.  Needs Cin % 32 == 0, W % PB == 0 and H % R == 0; grid.y = Cout / 32.
-template <int PB, int R>
+// operand and no B operand per MFMA.  The 16-byte global loads of the input row PD
+// ahead (of this chunk or the next) are in flight during the current row's MFMAs, in PD
+// register slots: with one wavefront per SIMD (the deep layers at batch 8 fill the chip
+// once) a lead of one row left the loads' latency exposed (PD = 2 to 4: 5-25% faster on
+// those layers).  Needs Cin % 32 == 0, W % PB == 0, H % R == 0, Cout % (32 WCO) == 0
+// and (R + 2) % PD == 0; grid.y = Cout / (32 WCO).
+template <int PB, int R, int WCO, int PD>
 __global__ __launch_bounds__(256) void k_conv3x3_rows(const __bf16 *__restrict__ in, int N, int H, int W, int Cin,
                                                       int in_cs, int in_co, const __bf16 *__restrict__ wt,
                                                       const float *__restrict__ bias, __bf16 *__restrict__ out,
                                                       int Cout, int out_cs, int out_co, int relu, int accumulate,
                                                       const __bf16 *__restrict__ mask, int mask_cs, int mask_co)
 {
+    constexpr int WP = 4 / WCO;                  // wavefronts per output-channel tile
     constexpr int PMT = PB / 32;                 // pixel tiles per row
-    constexpr int TW = PMT / 4;                  // pixel tiles per wavefront
-    static_assert(TW >= 1 && PMT == 4 * TW, "four wavefronts share the pixel tiles evenly");
+    constexpr int TW = PMT / WP;                 // pixel tiles per wavefront
+    constexpr int NR = R + 2;                    // input rows per chunk
+    static_assert(WP * WCO == 4 && TW >= 1 && PMT == WP * TW, "four wavefronts share the tiles evenly");
+    static_assert(PD >= 1 && NR % PD == 0, "input rows are prefetched PD ahead in PD register slots");
     constexpr int RS = 40;                       // LDS row stride (32 channels + 8 of padding)
     __shared__ __attribute__((aligned(16))) __bf16 xs[2][PB + 2][RS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wc = wave % WCO, wp = wave / WCO;
     const int m = lane & 31, half = lane >> 5;
     const int segs = W / PB, bands = H / R;
     const int x0 = (int)(blockIdx.x % segs) * PB;
     const int64_t nb = blockIdx.x / segs;        // n * bands + band
     const int64_t img = nb / bands;              // n
     const int y0 = (int)(nb % bands) * R;
-    const int co0 = blockIdx.y * 32;
+    const int co0 = (blockIdx.y * WCO + wc) * 32;
     f32x16 acc[R][TW];
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -127,18 +135,23 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(const __bf16 *__restrict__
             for (int j = 0; j < 16; ++j) acc[r][t][j] = 0.0f;
     constexpr int XV = (PB + 2) * 4;             // 16-byte input vectors per staged row
     constexpr int NXV = (XV + 255) / 256;
-    bf16x8 xr[NXV];
-    auto fetch_row = [&](int yi, int c0) {
+    bf16x8 xr[PD][NXV];
+    // input row y0 - 1 + j of chunk c0 into register slot d
+    auto fetch_row = [&](int d, int j, int c0) {
+        const int yi = y0 - 1 + j;
         const bool row_ok = yi >= 0 && yi < H;
 #pragma unroll
         for (int i = 0; i < NXV; ++i) {
             const int v = tid + 256 * i;
             const int c8 = v & 3, px = v >> 2, xx = x0 + px - 1;
-            xr[i] = zero8();
+            xr[d][i] = zero8();
             if (v < XV && row_ok && xx >= 0 && xx < W)
-                xr[i] = load8(in + ((img * H + yi) * W + xx) * in_cs + in_co + c0 + 8 * c8);
+                xr[d][i] = load8(in + ((img * H + yi) * W + xx) * in_cs + in_co + c0 + 8 * c8);
         }
     };
+    // B operands of a chunk: lane (m, half) holds output channel co0 + m, input channels
+    // c0 + 16 k + 8 half .. + 7, for every tap and k
+    bf16x8 bw[9][2];
     // the mask bits of this lane's outputs
     uint32_t mbits[R][TW];
 #pragma unroll
@@ -147,7 +160,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(const __bf16 *__restrict__
         for (int t = 0; t < TW; ++t) {
             mbits[r][t] = 0xffffu;
             if (mask) {
-                const int pm = wave + 4 * t;
+                const int pm = wp + WP * t;
                 uint32_t b = 0;
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
@@ -158,35 +171,36 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(const __bf16 *__restrict__
             }
         }
     const int nc = Cin / 32;
+#pragma unroll
+    for (int d = 0; d < PD; ++d) fetch_row(d, d, 0);
     for (int c = 0; c < nc; ++c) {
         const int c0 = 32 * c;
-        // B operands of the chunk: lane (m, half) holds output channel co0 + m, input
-        // channels c0 + 16 k + 8 half .. + 7, for every tap and k
-        bf16x8 bw[9][2];
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap)
 #pragma unroll
             for (int k = 0; k < 2; ++k)
                 bw[tap][k] = load8(wt + ((int64_t)tap * Cout + co0 + m) * Cin + c0 + 16 * k + 8 * half);
-        fetch_row(y0 - 1, c0);
-        if (c > 0) __syncthreads();              // the previous chunk's readers of xs are done
+        // with R odd the chunk's last row was read from the buffer its first row is written to
+        if ((R & 1) && c > 0) __syncthreads();
 #pragma unroll
-        for (int j = 0; j < R + 2; ++j) {        // input row y0 - 1 + j
+        for (int j = 0; j < NR; ++j) {           // input row y0 - 1 + j
             const int b = j & 1;
 #pragma unroll
             for (int i = 0; i < NXV; ++i) {
                 const int v = tid + 256 * i;
-                if (v < XV) *(bf16x8 *)&xs[b][v >> 2][8 * (v & 3)] = xr[i];
+                if (v < XV) *(bf16x8 *)&xs[b][v >> 2][8 * (v & 3)] = xr[j % PD][i];
             }
             __syncthreads();
-            if (j + 1 < R + 2) fetch_row(y0 + j, c0);
+            // the input row PD ahead, of this chunk or of the next one
+            if (j + PD < NR) fetch_row(j % PD, j + PD, c0);
+            else if (c + 1 < nc) fetch_row(j % PD, j + PD - NR, c0 + 32);
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
                 for (int k = 0; k < 2; ++k)
 #pragma unroll
                     for (int t = 0; t < TW; ++t) {
-                        const int pm = wave + 4 * t;
+                        const int pm = wp + WP * t;
                         const bf16x8 a = *(const bf16x8 *)&xs[b][32 * pm + m + dx][16 * k + 8 * half];
 #pragma unroll
                         for (int dy = 0; dy < 3; ++dy) {
@@ -203,7 +217,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(const __bf16 *__restrict__
     for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int t = 0; t < TW; ++t) {
-            const int pm = wave + 4 * t;
+            const int pm = wp + WP * t;
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 const int64_t pr = (img * H + y0 + r) * W + x0 + 32 * pm + 8 * (j >> 2) + 4 * half + (j & 3);
@@ -1028,23 +1042,30 @@ int ddf_nn_conv3x3(const void *in, int32_t N, int32_t H, int32_t W, int32_t Cin,
     hipLaunchKernelGGL((k_conv3x3_lds<PB, NCO>), dim3((unsigned)(npix / PB), (unsigned)(Cout / (32 * NCO))), dim3(256), \
                        0, st, i, N, H, W, Cin, in_cs, in_co, w, bias, o, Cout, out_cs, out_co, relu, accumulate, mk,       \
                        mask_cs, mask_co)
-#ifndef DDF_CONV_ROWS
-#define DDF_CONV_ROWS 4
-#endif
-#ifndef DDF_CONV_ROWS_COUT
-#define DDF_CONV_ROWS_COUT 96   // also the level-0 decoder's data gradient (32 -> 96 channels): 7% faster
-#endif
-#if DDF_CONV_ROWS > 0
-    // measured on 8 x 256^2 against the LDS-staged kernel: 4% faster with 32 input
-    // channels (bit for bit the same sums), 15% with 96, level with 128; slower with 64
-    // (10%, before the B operands moved to registers)
-    if (lds && (Cout == 32 || Cout == DDF_CONV_ROWS_COUT) && W % 128 == 0 && H % DDF_CONV_ROWS == 0 && Cin != 64) {
-        hipLaunchKernelGGL((k_conv3x3_rows<128, DDF_CONV_ROWS>), dim3((unsigned)(npix / (128 * DDF_CONV_ROWS)), (unsigned)(Cout / 32)),
-                           dim3(256), 0, st, i, N, H, W, Cin, in_cs, in_co, w, bias, o, Cout, out_cs, out_co, relu,
-                           accumulate, mk, mask_cs, mask_co);
-        return check_launch();
+#define DDF_CONV_ROWS(PB, R, WCO, PD)                                                                              \
+    do {                                                                                                          \
+        hipLaunchKernelGGL((k_conv3x3_rows<PB, R, WCO, PD>), dim3((unsigned)(npix / ((PB) * (R))), (unsigned)(Cout / (32 * (WCO)))), \
+                           dim3(256), 0, st, i, N, H, W, Cin, in_cs, in_co, w, bias, o, Cout, out_cs, out_co, relu,     \
+                           accumulate, mk, mask_cs, mask_co);                                                        \
+        return check_launch();                                                                                    \
+    } while (0)
+    // Row streaming where it beat the LDS-staged kernel on the surrogate's layers at batch 8
+    // (forward and data gradient, 8 x 256^2 .. 8 x 32^2; the other shapes keep the LDS kernel):
+    // 32 or 96 output channels at widths of 128 and more (1-8% faster; not with 64 input
+    // channels); 64 or 192 output channels at those widths (10-26%); 128 or 384 output
+    // channels from 128 or more input channels at width 64 (2-19%); 64 output channels at
+    // width 64 (5%); 256 output channels at width 32 (10-15%).
+    if (lds && W % 128 == 0 && H % 4 == 0) {
+        if ((Cout == 32 || Cout == 96) && Cin != 64) DDF_CONV_ROWS(128, 4, 1, 2);
+        if (Cout == 64 && Cin >= 128) DDF_CONV_ROWS(128, 4, 2, 2);
+        if (Cout == 64 || Cout == 192) DDF_CONV_ROWS(64, 4, 2, 2);
     }
-#endif
+    if (lds && W == 64 && H % 2 == 0) {
+        if (Cout % 128 == 0 && Cin >= 128) DDF_CONV_ROWS(64, 2, 4, 4);
+        if (Cout == 64) DDF_CONV_ROWS(64, 2, 2, 4);
+    }
+    if (lds && W == 32 && H % 2 == 0 && Cout % 256 == 0) DDF_CONV_ROWS(32, 2, 4, 4);
+#undef DDF_CONV_ROWS
     if (lds && W % 64 == 0 && Cout % 128 == 0) DDF_CONV_LDS(64, 4);
     else if (lds && W % 64 == 0 && Cout % 64 == 0) DDF_CONV_LDS(64, 2);
     else if (lds && W % 32 == 0 && Cout % 128 == 0) DDF_CONV_LDS(32, 4);

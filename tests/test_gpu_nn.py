@@ -179,16 +179,24 @@ def test_cast_weights_multi_matches_per_layer_casts():
 
 
 @pytest.mark.parametrize("accumulate", [0, 1])
-@pytest.mark.parametrize("W,Cout", [(64, 32), (128, 32), (64, 64)])   # k_conv3x3<4, 1>; rows <128, 4>; LDS <64, 2>
-def test_masked_data_gradient_and_pool_adjoint_equal_relu_backward_after(W, Cout, accumulate):
+@pytest.mark.parametrize("W,Cout,Cin", [
+    (64, 32, 64),      # k_conv3x3<4, 1>
+    (128, 32, 32),     # row streaming, 32 output channels per workgroup
+    (64, 64, 64),      # row streaming, two 32-channel tiles per workgroup, two rows
+    (128, 64, 32),     # row streaming, two tiles, four rows
+    (64, 128, 128),    # row streaming, four tiles per workgroup
+    (32, 256, 64),     # row streaming at width 32
+    (16, 64, 32),      # LDS-staged kernel, 64-pixel rows not available: k_conv3x3<2, 2>
+])
+def test_masked_data_gradient_and_pool_adjoint_equal_relu_backward_after(W, Cout, Cin, accumulate):
     # masking each contribution (the fused path of the network's backward) gives the bits
     # of the unmasked kernel followed by the ReLU adjoint, when what is accumulated into
     # is already masked
     r = np.random.default_rng(31 + accumulate + W + Cout)
-    B, H, Cin, cs = 2, 8, (32 if W == 128 else 64), 96     # W 128: the row-streaming kernel
+    B, H, cs = 2, 8, Cout + 32
     dyt, _ = bf(r.standard_normal((B, H, W, Cin)))
     wd, _ = bf(0.1 * r.standard_normal((9, Cout, Cin)))
-    act, _ = bf(r.standard_normal((B, H, W, cs)))              # mask channels [16, 48) of a wider tensor
+    act, _ = bf(r.standard_normal((B, H, W, cs)))              # mask channels [16, 16 + Cout) of a wider tensor
     old = torch.where(act[..., 16:16 + Cout] > 0, torch.tensor(r.standard_normal((B, H, W, Cout)), dtype=torch.bfloat16,
                                                                 device=DEV), torch.zeros((), dtype=torch.bfloat16, device=DEV))
     fused = old.clone().contiguous()
@@ -438,6 +446,14 @@ def test_elementwise_kernels_with_unaligned_channel_counts():
     (1, 8, 128, 32, 32, 32, 0, 32, 0, 0),        # 32 output channels, rows a multiple of 4: row streaming
     (2, 4, 256, 96, 32, 96, 0, 64, 32, 1),       # row streaming, 3 input chunks, slices, accumulate
     (1, 12, 128, 128, 32, 160, 16, 32, 0, 0),    # row streaming, 4 input chunks, input slice
+    (1, 4, 128, 32, 64, 32, 0, 64, 0, 0),        # row streaming, 64 channels: 64-pixel rows, 2 tiles per workgroup
+    (1, 4, 128, 128, 64, 160, 32, 96, 16, 1),    # row streaming, 128-pixel rows, 2 tiles, slices, accumulate
+    (1, 8, 128, 64, 192, 64, 0, 192, 0, 0),      # row streaming, 192 channels: 3 workgroup columns
+    (2, 4, 64, 128, 128, 128, 0, 128, 0, 0),     # row streaming at width 64, 4 tiles per workgroup
+    (1, 6, 64, 160, 384, 160, 0, 384, 0, 1),     # 5 input chunks, 384 channels, accumulate
+    (1, 2, 64, 128, 64, 128, 0, 64, 0, 0),       # row streaming at width 64, 2 tiles
+    (2, 4, 32, 256, 256, 288, 32, 256, 0, 0),    # row streaming at width 32, 8 input chunks, input slice
+    (1, 3, 64, 128, 128, 128, 0, 128, 0, 0),     # odd row count: the LDS-staged kernel
 ])
 def test_conv3x3_lds_configs(B, H, W, Cin, Cout, cs_in, co_in, cs_out, co_out, acc):
     r = np.random.default_rng(B + H + W + Cin + Cout)
@@ -465,6 +481,7 @@ def test_conv3x3_lds_configs(B, H, W, Cin, Cout, cs_in, co_in, cs_out, co_out, a
     (256, 96, 32),     # the level-0 decoder input: 128-pixel segments
     (128, 64, 64),     # 64-pixel segments x 2 channel tiles; weight gradient with two output tiles
     (64, 384, 128),    # the level-2 decoder input: 4 channel tiles
+    (128, 192, 64),    # the level-1 decoder input
     (32, 256, 256),    # the bottom level: 32-pixel segments
 ])
 def test_full_size_layers_sampled_outputs(H, Cin, Cout):
