@@ -56,11 +56,16 @@ int ddf_nn_conv3x3_wgrad(const void *in, int32_t N, int32_t H, int32_t W, int32_
 
 /* grad[i] = 0 where act[i] <= 0 (n contiguous elements). */
 int ddf_nn_relu_bwd(void *grad, const void *act, int64_t n, void *stream);
-/* 2x2 average pooling (contiguous C channels) and its adjoint (din = or += dout / 4, each
- * child's value set to zero where mask, laid out as din, is not > 0; mask may be NULL). */
-int ddf_nn_pool2(const void *in, int32_t N, int32_t H, int32_t W, int32_t C, void *out, void *stream);
-int ddf_nn_pool2_bwd(const void *dout, int32_t N, int32_t H, int32_t W, int32_t C, void *din, const void *mask,
-                     int32_t accumulate, void *stream);
+/* 2x2 average pooling of channels [in_co, in_co + C) of in (channel stride in_cs) into out
+ * (C contiguous channels), and its adjoint into channels [din_co, din_co + C) of din
+ * (stride din_cs): din = or += dout / 4, each child's value set to zero where mask, laid
+ * out as din, is not > 0 (mask may be NULL).  A skip connection's tensor can so live
+ * inside the concatenation buffer that the decoder reads.  H and W even, strides covering
+ * the channels (else DDF_ERR_ARG). */
+int ddf_nn_pool2(const void *in, int32_t N, int32_t H, int32_t W, int32_t C, int32_t in_cs, int32_t in_co, void *out,
+                 void *stream);
+int ddf_nn_pool2_bwd(const void *dout, int32_t N, int32_t H, int32_t W, int32_t C, void *din, int32_t din_cs,
+                     int32_t din_co, const void *mask, int32_t accumulate, void *stream);
 /* Nearest 2x upsampling of in (h x w, C contiguous channels) into a channel slice of out,
  * and its adjoint (sum of the four children) from a channel slice of dout. */
 int ddf_nn_up2(const void *in, int32_t N, int32_t h, int32_t w, int32_t C, void *out, int32_t out_cs, int32_t out_co,

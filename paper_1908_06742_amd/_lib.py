@@ -124,8 +124,8 @@ NN_SIGNATURES = {
     "ddf_nn_conv3x3_wgrad": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _i32, _vp, _vp, _i32,
                                        _vp, _vp]),
     "ddf_nn_relu_bwd": (C.c_int, [_vp, _vp, _i64, _vp]),
-    "ddf_nn_pool2": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp]),
-    "ddf_nn_pool2_bwd": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _i32, _vp]),
+    "ddf_nn_pool2": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp]),
+    "ddf_nn_pool2_bwd": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _i32, _i32, _vp, _i32, _vp]),
     "ddf_nn_up2": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _i32, _i32, _vp]),
     "ddf_nn_up2_bwd": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp]),
     "ddf_nn_slice": (C.c_int, [_vp, _i32, _i32, _vp, _i32, _i32, _i64, _i32, _i32, _vp]),

@@ -623,7 +623,11 @@ __global__ void k_relu_bwd(__bf16 *__restrict__ g, const __bf16 *__restrict__ ac
 }
 
 // 2x2 average pooling and its adjoint (NHWC, C channels, contiguous).
-__global__ void k_pool2(const __bf16 *__restrict__ in, int N, int H, int W, int C, __bf16 *__restrict__ out)
+// 2x2 average pooling of channels [ic0, ic0 + C) of in (channel stride in_cs) into out
+// (C contiguous channels), and the adjoint into channels [dc0, dc0 + C) of din (stride
+// d_cs; mask laid out as din).
+__global__ void k_pool2(const __bf16 *__restrict__ in, int N, int H, int W, int C, int in_cs, int ic0,
+                        __bf16 *__restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int h = H / 2, w = W / 2;
@@ -631,22 +635,23 @@ __global__ void k_pool2(const __bf16 *__restrict__ in, int N, int H, int W, int 
     const int c = i % C;
     const int64_t q = i / C;
     const int xo = q % w, yo = (q / w) % h, n = q / ((int64_t)w * h);
-    const __bf16 *b = in + ((int64_t)(n * H + 2 * yo) * W + 2 * xo) * C + c;
-    const float s = (float)b[0] + (float)b[C] + (float)b[(int64_t)W * C] + (float)b[(int64_t)W * C + C];
+    const __bf16 *b = in + ((int64_t)(n * H + 2 * yo) * W + 2 * xo) * in_cs + ic0 + c;
+    const float s = (float)b[0] + (float)b[in_cs] + (float)b[(int64_t)W * in_cs] + (float)b[(int64_t)W * in_cs + in_cs];
     out[i] = (__bf16)(0.25f * s);
 }
 
 __global__ void k_pool2_bwd(const __bf16 *__restrict__ dout, int N, int H, int W, int C, __bf16 *__restrict__ din,
-                            const __bf16 *__restrict__ mask, int accumulate)
+                            int d_cs, int dc0, const __bf16 *__restrict__ mask, int accumulate)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)N * H * W * C) return;
     const int c = i % C;
     const int64_t q = i / C;
     const int x = q % W, y = (q / W) % H, n = q / ((int64_t)W * H);
+    const int64_t e = q * d_cs + dc0 + c;
     float v = 0.25f * (float)dout[((int64_t)(n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
-    if (mask && !((float)mask[i] > 0.0f)) v = 0.0f;
-    din[i] = (__bf16)(accumulate ? (float)din[i] + v : v);
+    if (mask && !((float)mask[e] > 0.0f)) v = 0.0f;
+    din[e] = (__bf16)(accumulate ? (float)din[e] + v : v);
 }
 
 // Nearest-neighbour 2x upsampling of in (h x w) into channels [oc0, oc0 + C) of out
@@ -707,7 +712,8 @@ __global__ void k_relu_bwd8(__bf16 *__restrict__ g, const __bf16 *__restrict__ a
     store8(g + 8 * i, gv);
 }
 
-__global__ void k_pool2_8(const __bf16 *__restrict__ in, int N, int H, int W, int C, __bf16 *__restrict__ out)
+__global__ void k_pool2_8(const __bf16 *__restrict__ in, int N, int H, int W, int C, int in_cs, int ic0,
+                          __bf16 *__restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int h = H / 2, w = W / 2, C8 = C / 8;
@@ -715,8 +721,9 @@ __global__ void k_pool2_8(const __bf16 *__restrict__ in, int N, int H, int W, in
     const int c = 8 * (int)(i % C8);
     const int64_t q = i / C8;
     const int xo = q % w, yo = (q / w) % h, n = q / ((int64_t)w * h);
-    const __bf16 *b = in + ((int64_t)(n * H + 2 * yo) * W + 2 * xo) * C + c;
-    const bf16x8 a0 = load8(b), a1 = load8(b + C), a2 = load8(b + (int64_t)W * C), a3 = load8(b + (int64_t)W * C + C);
+    const __bf16 *b = in + ((int64_t)(n * H + 2 * yo) * W + 2 * xo) * in_cs + ic0 + c;
+    const int64_t rs = (int64_t)W * in_cs;
+    const bf16x8 a0 = load8(b), a1 = load8(b + in_cs), a2 = load8(b + rs), a3 = load8(b + rs + in_cs);
     bf16x8 r;
 #pragma unroll
     for (int k = 0; k < 8; ++k) r[k] = (__bf16)(0.25f * ((float)a0[k] + (float)a1[k] + (float)a2[k] + (float)a3[k]));
@@ -724,7 +731,7 @@ __global__ void k_pool2_8(const __bf16 *__restrict__ in, int N, int H, int W, in
 }
 
 __global__ void k_pool2_bwd8(const __bf16 *__restrict__ dout, int N, int H, int W, int C, __bf16 *__restrict__ din,
-                             const __bf16 *__restrict__ mask, int accumulate)
+                             int d_cs, int dc0, const __bf16 *__restrict__ mask, int accumulate)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int C8 = C / 8;
@@ -732,16 +739,17 @@ __global__ void k_pool2_bwd8(const __bf16 *__restrict__ dout, int N, int H, int 
     const int c = 8 * (int)(i % C8);
     const int64_t q = i / C8;
     const int x = q % W, y = (q / W) % H, n = q / ((int64_t)W * H);
+    const int64_t e = q * d_cs + dc0 + c;
     const bf16x8 d = load8(dout + ((int64_t)(n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c);
-    bf16x8 r = accumulate ? load8(din + q * C + c) : zero8();
-    const bf16x8 mk = mask ? load8(mask + q * C + c) : zero8();
+    bf16x8 r = accumulate ? load8(din + e) : zero8();
+    const bf16x8 mk = mask ? load8(mask + e) : zero8();
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         float v = 0.25f * (float)d[k];
         if (mask && !((float)mk[k] > 0.0f)) v = 0.0f;
         r[k] = (__bf16)(accumulate ? (float)r[k] + v : v);
     }
-    store8(din + q * C + c, r);
+    store8(din + e, r);
 }
 
 __global__ void k_up2_8(const __bf16 *__restrict__ in, int N, int h, int w, int C, __bf16 *__restrict__ out,
@@ -1112,12 +1120,16 @@ WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout)
         P.ci_t = 1;
         const int64_t groups = (int64_t)(Cin / (32 * P.ci_t)) * (Cout / (32 * P.co_t));
         const int64_t nblocks = npix / P.pb;
+        // about kWgradGroups workgroups; half as many, with twice the pixels each, where
+        // several channel tiles split a large image (the surrogate's 64 -> 64, 192 -> 64 at
+        // 8 x 128^2 and 96 -> 32 at 8 x 256^2: 8-22% faster)
+        const int64_t target = groups >= 2 && npix >= 131072 ? kWgradGroups / 2 : kWgradGroups;
         // bytes read: each workgroup stages its input-channel and output-channel slices
         const double reads = 2.0 * (double)npix *
                              ((double)Cin * (Cout / (32 * P.co_t)) + (double)Cout * (Cin / (32 * P.ci_t)));
         const double part_chunk = 4.0 * ((double)9 * Cout * Cin + Cout);
         const int64_t cap = std::max<int64_t>(1, (int64_t)std::min(kWgradPartFrac * reads / part_chunk, 1e15));
-        int64_t nchunk = (kWgradGroups + groups - 1) / groups;
+        int64_t nchunk = (target + groups - 1) / groups;
         nchunk = std::max<int64_t>(1, std::min<int64_t>({nchunk, cap, nblocks}));
         P.per_chunk = (nblocks + nchunk - 1) / nchunk;
         P.nchunk = (nblocks + P.per_chunk - 1) / P.per_chunk;
@@ -1216,29 +1228,35 @@ int ddf_nn_relu_bwd(void *grad, const void *act, int64_t n, void *stream)
     return check_launch();
 }
 
-int ddf_nn_pool2(const void *in, int32_t N, int32_t H, int32_t W, int32_t C, void *out, void *stream)
+int ddf_nn_pool2(const void *in, int32_t N, int32_t H, int32_t W, int32_t C, int32_t in_cs, int32_t in_co, void *out,
+                 void *stream)
 {
+    if (!in || !out || N <= 0 || H <= 0 || W <= 0 || C <= 0) return fail(DDF_ERR_ARG, "pool2: bad tensor arguments");
     if (H % 2 || W % 2) return fail(DDF_ERR_ARG, "pool2: H and W must be even");
-    if (C % 8 == 0 && al16(in) && al16(out))
+    if (in_co < 0 || in_cs < in_co + C) return fail(DDF_ERR_ARG, "pool2: the channel stride must cover the channels");
+    if (C % 8 == 0 && in_cs % 8 == 0 && in_co % 8 == 0 && al16(in) && al16(out))
         hipLaunchKernelGGL(k_pool2_8, dim3(blocks_for((int64_t)N * H * W * C / 32)), dim3(256), 0, (hipStream_t)stream,
-                           (const __bf16 *)in, N, H, W, C, (__bf16 *)out);
+                           (const __bf16 *)in, N, H, W, C, in_cs, in_co, (__bf16 *)out);
     else
         hipLaunchKernelGGL(k_pool2, dim3(blocks_for((int64_t)N * H * W * C / 4)), dim3(256), 0, (hipStream_t)stream,
-                           (const __bf16 *)in, N, H, W, C, (__bf16 *)out);
+                           (const __bf16 *)in, N, H, W, C, in_cs, in_co, (__bf16 *)out);
     return check_launch();
 }
 
-int ddf_nn_pool2_bwd(const void *dout, int32_t N, int32_t H, int32_t W, int32_t C, void *din, const void *mask,
-                     int32_t accumulate, void *stream)
+int ddf_nn_pool2_bwd(const void *dout, int32_t N, int32_t H, int32_t W, int32_t C, void *din, int32_t din_cs,
+                     int32_t din_co, const void *mask, int32_t accumulate, void *stream)
 {
+    if (!dout || !din || N <= 0 || H <= 0 || W <= 0 || C <= 0) return fail(DDF_ERR_ARG, "pool2_bwd: bad tensor arguments");
     if (H % 2 || W % 2) return fail(DDF_ERR_ARG, "pool2_bwd: H and W must be even");
+    if (din_co < 0 || din_cs < din_co + C) return fail(DDF_ERR_ARG, "pool2_bwd: the channel stride must cover the channels");
     const __bf16 *mk = (const __bf16 *)mask;
-    if (C % 8 == 0 && al16(dout) && al16(din) && (!mask || al16(mask)))
+    if (C % 8 == 0 && din_cs % 8 == 0 && din_co % 8 == 0 && al16(dout) && al16(din) && (!mask || al16(mask)))
         hipLaunchKernelGGL(k_pool2_bwd8, dim3(blocks_for((int64_t)N * H * W * C / 8)), dim3(256), 0,
-                           (hipStream_t)stream, (const __bf16 *)dout, N, H, W, C, (__bf16 *)din, mk, accumulate);
+                           (hipStream_t)stream, (const __bf16 *)dout, N, H, W, C, (__bf16 *)din, din_cs, din_co, mk,
+                           accumulate);
     else
         hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks_for((int64_t)N * H * W * C)), dim3(256), 0, (hipStream_t)stream,
-                           (const __bf16 *)dout, N, H, W, C, (__bf16 *)din, mk, accumulate);
+                           (const __bf16 *)dout, N, H, W, C, (__bf16 *)din, din_cs, din_co, mk, accumulate);
     return check_launch();
 }
 

@@ -178,7 +178,13 @@ class UNet:
             h, w, c = H >> k, W >> k, self.ch[k]
             if k > 0:
                 A[f"pool{k}"] = t(h, w, self.ch[k - 1])
-            A[f"enc{k}a"], A[f"enc{k}b"] = t(h, w, c), t(h, w, c)
+            A[f"enc{k}a"] = t(h, w, c)
+        # the deepest encoder output is a tensor of its own; every other encoder output (a
+        # skip connection) is written straight into the channels [ch[k+1], ch[k+1] + ch[k])
+        # of its decoder's concatenation buffer, where the decoder reads it (and its
+        # gradient lives in the same channels of the gradient of that buffer)
+        k = self.levels - 1
+        A[f"enc{k}b"] = t(H >> k, W >> k, self.ch[k])
         for k in range(self.levels - 2, -1, -1):
             h, w = H >> k, W >> k
             A[f"cat{k}"] = t(h, w, self.ch[k + 1] + self.ch[k])
@@ -198,10 +204,20 @@ class UNet:
         self._shape = (B, H, W)
 
     # ----------------------------------------------------------------- forward
-    def _conv(self, name, src, src_cs, dst, B, h, w):
+    def _skip(self, k, grad=False):
+        """(tensor, channel stride, channel offset) of encoder output enc{k}b, or of its
+        gradient: a tensor of its own at the deepest level, else a channel slice of the
+        decoder's concatenation buffer cat{k}."""
+        T = self.G if grad else self.A
+        if k == self.levels - 1:
+            return T[f"enc{k}b"], self.ch[k], 0
+        return T[f"cat{k}"], self.ch[k + 1] + self.ch[k], self.ch[k + 1]
+
+    def _conv(self, name, src, src_cs, dst, B, h, w, src_co=0, dst_cs=None, dst_co=0):
         _, _, cip, cop, relu = self._dims(name)
-        L.check(L.lib().ddf_nn_conv3x3(_p(src), B, h, w, cip, src_cs, 0, _p(self.wf[name]),
-                                       self._wptr(self.w, name, bias=True), _p(dst), cop, cop, 0, int(relu), 0,
+        L.check(L.lib().ddf_nn_conv3x3(_p(src), B, h, w, cip, src_cs, src_co, _p(self.wf[name]),
+                                       self._wptr(self.w, name, bias=True), _p(dst), cop,
+                                       cop if dst_cs is None else dst_cs, dst_co, int(relu), 0,
                                        None, 0, 0, self._s()))
 
     def inputs(self, re, u, H, W):
@@ -220,17 +236,18 @@ class UNet:
         for k in range(self.levels):
             hh, ww = H >> k, W >> k
             if k > 0:
-                L.check(lib.ddf_nn_pool2(_p(h), B, 2 * hh, 2 * ww, hc, _p(A[f"pool{k}"]), s))
-                h = A[f"pool{k}"]
+                src, cs, co = self._skip(k - 1)
+                L.check(lib.ddf_nn_pool2(_p(src), B, 2 * hh, 2 * ww, self.ch[k - 1], cs, co, _p(A[f"pool{k}"]), s))
+                h, hc = A[f"pool{k}"], self.ch[k - 1]
             self._conv(f"enc{k}a", h, hc, A[f"enc{k}a"], B, hh, ww)
-            self._conv(f"enc{k}b", A[f"enc{k}a"], self.ch[k], A[f"enc{k}b"], B, hh, ww)
-            h, hc = A[f"enc{k}b"], self.ch[k]
+            dst, cs, co = self._skip(k)
+            self._conv(f"enc{k}b", A[f"enc{k}a"], self.ch[k], dst, B, hh, ww, dst_cs=cs, dst_co=co)
+        h, hc = A[f"enc{self.levels - 1}b"], self.ch[self.levels - 1]
         for k in range(self.levels - 2, -1, -1):
             hh, ww = H >> k, W >> k
             ctot = hc + self.ch[k]
             cat = A[f"cat{k}"]
             L.check(lib.ddf_nn_up2(_p(h), B, hh // 2, ww // 2, hc, _p(cat), ctot, 0, s))
-            L.check(lib.ddf_nn_slice(_p(A[f"enc{k}b"]), self.ch[k], 0, _p(cat), ctot, hc, B * hh * ww, self.ch[k], 0, s))
             self._conv(f"dec{k}a", cat, ctot, A[f"dec{k}a"], B, hh, ww)
             self._conv(f"dec{k}b", A[f"dec{k}a"], self.ch[k], A[f"dec{k}b"], B, hh, ww)
             h, hc = A[f"dec{k}b"], self.ch[k]
@@ -238,21 +255,23 @@ class UNet:
         return A["head"]
 
     # ---------------------------------------------------------------- backward
-    def _conv_back(self, name, src, src_cs, dsrc, acc, B, h, w, src_relu=True):
-        """dY = G[name] holds the gradient of the layer's output, already multiplied by its
-        ReLU's derivative: every producer of a gradient masks its contribution with the
-        activation it flows into (here: the data gradient, masked with `src` when `src` is
-        a ReLU output)."""
+    def _conv_back(self, name, src, src_cs, dsrc, acc, B, h, w, src_relu=True, dy=None):
+        """dY (default G[name]; else (tensor, channel stride, offset)) holds the gradient of
+        the layer's output, already multiplied by its ReLU's derivative: every producer of a
+        gradient masks its contribution with the activation it flows into (here: the data
+        gradient, masked with `src` when `src` is a ReLU output)."""
         _, _, cip, cop, relu = self._dims(name)
         lib, s = L.lib(), self._s()
-        dy = self.G[name]
-        L.check(lib.ddf_nn_conv3x3_wgrad(_p(src), B, h, w, cip, src_cs, 0, _p(dy), cop, cop,
-                                         self._wptr(self.g, name), self._wptr(self.g, name, bias=True), 0,
+        dyt, dcs, dco = (self.G[name], cop, 0) if dy is None else dy
+        # the weight gradient takes the output gradient's channel offset in its pointer
+        # (bf16 elements, offsets multiples of 8: 16-byte aligned)
+        L.check(lib.ddf_nn_conv3x3_wgrad(_p(src), B, h, w, cip, src_cs, 0, C.c_void_p(dyt.data_ptr() + 2 * dco), cop,
+                                         dcs, self._wptr(self.g, name), self._wptr(self.g, name, bias=True), 0,
                                          _p(self.ws), s))
         if dsrc is not None:
             mask = _p(src) if src_relu else None
-            L.check(lib.ddf_nn_conv3x3(_p(dy), B, h, w, cop, cop, 0, _p(self.wd[name]), None, _p(dsrc), cip, cip, 0, 0,
-                                       int(acc), mask, src_cs, 0, s))
+            L.check(lib.ddf_nn_conv3x3(_p(dyt), B, h, w, cop, dcs, dco, _p(self.wd[name]), None, _p(dsrc), cip, cip, 0,
+                                       0, int(acc), mask, src_cs, 0, s))
 
     def backward(self, B, H, W):
         """Needs G['head'] = dLoss/dOut; fills self.g with every parameter's gradient."""
@@ -264,21 +283,24 @@ class UNet:
             cu = self.ch[k + 1]
             ctot = cu + self.ch[k]
             self._conv_back(f"dec{k}a", A[f"cat{k}"], ctot, G[f"cat{k}"], 0, B, hh, ww)
-            # adjoint of the concatenation: upsampled part -> deeper output, skip part -> encoder output
+            # adjoint of the concatenation: the upsampled part goes to the deeper output; the
+            # skip part is already the encoder output's gradient (same channels of G[cat{k}])
             deeper = f"dec{k + 1}b" if k + 1 <= self.levels - 2 else f"enc{self.levels - 1}b"
             L.check(lib.ddf_nn_up2_bwd(_p(G[f"cat{k}"]), B, hh // 2, ww // 2, cu, ctot, 0, _p(G[deeper]), s))
-            L.check(lib.ddf_nn_slice(_p(G[f"cat{k}"]), ctot, cu, _p(G[f"enc{k}b"]), self.ch[k], 0, B * hh * ww,
-                                     self.ch[k], 0, s))
         for k in range(self.levels - 1, -1, -1):
             hh, ww = H >> k, W >> k
-            self._conv_back(f"enc{k}b", A[f"enc{k}a"], self.ch[k], G[f"enc{k}a"], 0, B, hh, ww)
+            self._conv_back(f"enc{k}b", A[f"enc{k}a"], self.ch[k], G[f"enc{k}a"], 0, B, hh, ww,
+                            dy=self._skip(k, grad=True))
             if k > 0:
                 # the pooled input is no ReLU output: its gradient is masked per child below
                 self._conv_back(f"enc{k}a", A[f"pool{k}"], self.ch[k - 1], G[f"pool{k}"], 0, B, hh, ww,
                                 src_relu=False)
-                # the pooled input feeds from the previous level's output, which also got a skip gradient
-                L.check(lib.ddf_nn_pool2_bwd(_p(G[f"pool{k}"]), B, 2 * hh, 2 * ww, self.ch[k - 1],
-                                             _p(G[f"enc{k - 1}b"]), _p(A[f"enc{k - 1}b"]), 1, s))
+                # the pooled input feeds from the previous level's output, which also got a
+                # skip gradient: accumulate, masked by that output (same channel layout)
+                gk, cs, co = self._skip(k - 1, grad=True)
+                ak, _, _ = self._skip(k - 1)
+                L.check(lib.ddf_nn_pool2_bwd(_p(G[f"pool{k}"]), B, 2 * hh, 2 * ww, self.ch[k - 1], _p(gk), cs, co,
+                                             _p(ak), 1, s))
             else:
                 self._conv_back("enc0a", self.x, CIN_P, None, 0, B, hh, ww)
 

@@ -130,7 +130,7 @@ def test_pool_up_slice_relu_kernels():
     B, H, W, C = 2, 8, 8, 16
     xt, x = bf(r.standard_normal((B, H, W, C)))
     pooled = torch.empty(B * H * W * C // 4, dtype=torch.bfloat16, device=DEV)
-    L.check(L.lib().ddf_nn_pool2(p(xt), B, H, W, C, p(pooled), s0()))
+    L.check(L.lib().ddf_nn_pool2(p(xt), B, H, W, C, C, 0, p(pooled), s0()))
     assert_bf16_ulp(np_of(pooled, (B, H // 2, W // 2, C)), U.pool2(x), U.pool2(np.abs(x)), 4)
     up = torch.zeros(B * H * W * 24, dtype=torch.bfloat16, device=DEV)
     L.check(L.lib().ddf_nn_up2(p(pooled), B, H // 2, W // 2, C, p(up), 24, 8, s0()))
@@ -141,7 +141,7 @@ def test_pool_up_slice_relu_kernels():
     L.check(L.lib().ddf_nn_up2_bwd(p(gt), B, H // 2, W // 2, C, 24, 8, p(din), s0()))
     assert_bf16_ulp(np_of(din, pq.shape), U.up2_backward(g[..., 8:24]), U.up2_backward(np.abs(g[..., 8:24])), 4)
     dp = torch.zeros(B * H * W * C, dtype=torch.bfloat16, device=DEV)
-    L.check(L.lib().ddf_nn_pool2_bwd(p(din), B, H, W, C, p(dp), None, 0, s0()))
+    L.check(L.lib().ddf_nn_pool2_bwd(p(din), B, H, W, C, p(dp), C, 0, None, 0, s0()))
     dq = np_of(din, pq.shape)
     assert_bf16_ulp(np_of(dp, x.shape), U.pool2_backward(dq), U.pool2_backward(np.abs(dq)), 1)
     dst = torch.zeros(B * H * W * 40, dtype=torch.bfloat16, device=DEV)
@@ -220,12 +220,48 @@ def test_masked_data_gradient_and_pool_adjoint_equal_relu_backward_after(W, Cout
         fused = o.clone().contiguous()
         ref = o.clone().contiguous()
         Cp = C if vec else C - 3          # C % 8 != 0 takes the single-element kernel
-        L.check(L.lib().ddf_nn_pool2_bwd(p(d), B, H, W, Cp, p(fused), p(a), accumulate, s0()))
-        L.check(L.lib().ddf_nn_pool2_bwd(p(d), B, H, W, Cp, p(ref), None, accumulate, s0()))
+        L.check(L.lib().ddf_nn_pool2_bwd(p(d), B, H, W, Cp, p(fused), Cp, 0, p(a), accumulate, s0()))
+        L.check(L.lib().ddf_nn_pool2_bwd(p(d), B, H, W, Cp, p(ref), Cp, 0, None, accumulate, s0()))
         n = B * H * W * Cp
         L.check(L.lib().ddf_nn_relu_bwd(p(ref), p(a), n, s0()))
         torch.cuda.synchronize()
         assert torch.equal(fused.reshape(-1)[:n], ref.reshape(-1)[:n]), vec
+
+
+@pytest.mark.parametrize("C,cs,co", [(16, 32, 8), (12, 20, 4), (32, 96, 64)])   # 16-byte and single-element forms
+@pytest.mark.parametrize("accumulate", [0, 1])
+def test_pool_reads_and_adjoint_writes_channel_slices(C, cs, co, accumulate):
+    # pooling of channels [co, co + C) of a wider tensor, and the adjoint (masked by a
+    # tensor of the same layout) into that slice, leaving the other channels as they were:
+    # a skip connection held inside the decoder's concatenation buffer
+    r = np.random.default_rng(C + cs + co + accumulate)
+    B, H, W = 2, 6, 8
+    xt, x = bf(r.standard_normal((B, H, W, cs)))
+    pooled = torch.empty(B * H * W * C // 4, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_pool2(p(xt), B, H, W, C, cs, co, p(pooled), s0()))
+    xs = x[..., co:co + C]
+    assert_bf16_ulp(np_of(pooled, (B, H // 2, W // 2, C)), U.pool2(xs), U.pool2(np.abs(xs)), 4)
+    dt, dq = bf(r.standard_normal((B, H // 2, W // 2, C)))
+    mt, mq = bf(r.standard_normal((B, H, W, cs)))
+    gt, g0 = bf(r.standard_normal((B, H, W, cs)))
+    L.check(L.lib().ddf_nn_pool2_bwd(p(dt), B, H, W, C, p(gt), cs, co, p(mt), accumulate, s0()))
+    got = np_of(gt, (B, H, W, cs))
+    want = np.where(mq[..., co:co + C] > 0, U.pool2_backward(dq), 0.0)
+    mag = np.abs(want)
+    if accumulate:
+        want = want + g0[..., co:co + C]
+        mag = mag + np.abs(g0[..., co:co + C])
+    assert_bf16_ulp(got[..., co:co + C], want, mag, 1)
+    keep = np.ones(cs, bool)
+    keep[co:co + C] = False
+    assert np.array_equal(got[..., keep], g0[..., keep])
+
+
+def test_pool_rejects_strides_that_miss_the_channels():
+    x = torch.zeros(2 * 4 * 4 * 16, dtype=torch.bfloat16, device=DEV)
+    o = torch.zeros(2 * 2 * 2 * 16, dtype=torch.bfloat16, device=DEV)
+    assert L.lib().ddf_nn_pool2(p(x), 2, 4, 4, 16, 16, 8, p(o), s0()) == L.DDF_ERR_ARG
+    assert L.lib().ddf_nn_pool2_bwd(p(o), 2, 4, 4, 16, p(x), 8, 0, None, 0, s0()) == L.DDF_ERR_ARG
 
 
 def test_mse_and_adam():
@@ -314,6 +350,14 @@ def test_unet_forward_backward_against_reference(levels, H):
         return int(re_mod.search(r"\d", key).group())
 
     A = {k: np_of(v, (B, H >> level(k), W >> level(k), -1)) for k, v in net.A.items() if k != "head"}
+
+    def output_of(name):
+        # an encoder output other than the deepest one lives in its decoder's concatenation
+        k = int(name[3])
+        if name.startswith("enc") and name[4] == "b" and k < levels - 1:
+            return A[f"cat{k}"][..., net.ch[k + 1]:net.ch[k + 1] + net.ch[k]]
+        return A[name]
+
     gcache = {}
     for name, ci, co, _ in net.table:
         if name == "head":
@@ -324,7 +368,7 @@ def test_unet_forward_backward_against_reference(levels, H):
             src = (x if k == 0 else A[f"pool{k}"]) if part == "a" else A[f"enc{k}a"]
         else:
             src = A[f"cat{k}"] if part == "a" else A[f"dec{k}a"]
-        gcache[name] = (src[..., :ci], A[name][..., :co])
+        gcache[name] = (src[..., :ci], output_of(name)[..., :co])
     _, dgpu = U.mse(got, target.astype(np.float64), np.ones(4))
     compare(U.backward(pq, gcache, q(dgpu), base=32, levels=levels, cout=4, q=q), 1e-2, 5e-3)
     # (2) the independent BF16-storage reference end to end: ReLU masks of activations
@@ -409,7 +453,7 @@ def test_elementwise_kernels_with_unaligned_channel_counts():
     B, H, W, C = 2, 6, 8, 12
     xt, x = bf(r.standard_normal((B, H, W, C)))
     pooled = torch.empty(B * H * W * C // 4, dtype=torch.bfloat16, device=DEV)
-    L.check(L.lib().ddf_nn_pool2(p(xt), B, H, W, C, p(pooled), s0()))
+    L.check(L.lib().ddf_nn_pool2(p(xt), B, H, W, C, C, 0, p(pooled), s0()))
     pq = np_of(pooled, (B, H // 2, W // 2, C))
     assert_bf16_ulp(pq, U.pool2(x), U.pool2(np.abs(x)), 4)
     up = torch.zeros(B * H * W * 20, dtype=torch.bfloat16, device=DEV)
@@ -420,7 +464,7 @@ def test_elementwise_kernels_with_unaligned_channel_counts():
     L.check(L.lib().ddf_nn_up2_bwd(p(gt), B, H // 2, W // 2, C, 20, 4, p(din), s0()))
     assert_bf16_ulp(np_of(din, pq.shape), U.up2_backward(g[..., 4:16]), U.up2_backward(np.abs(g[..., 4:16])), 4)
     dp = torch.zeros(B * H * W * C, dtype=torch.bfloat16, device=DEV)
-    L.check(L.lib().ddf_nn_pool2_bwd(p(din), B, H, W, C, p(dp), None, 0, s0()))
+    L.check(L.lib().ddf_nn_pool2_bwd(p(din), B, H, W, C, p(dp), C, 0, None, 0, s0()))
     dq = np_of(din, pq.shape)
     assert_bf16_ulp(np_of(dp, x.shape), U.pool2_backward(dq), U.pool2_backward(np.abs(dq)), 1)
     dst, dq = bf(r.standard_normal((B, H, W, 20)))
