@@ -140,9 +140,7 @@ typedef struct ddf_handle ddf_handle;
 /* Row pitch in elements of every population plane: nx rounded up to 64, or nx for
  * DDF_LAYOUT_PACKED. */
 int64_t ddf_pitch(const ddf_params *p);
-/* Elements from one direction plane to the next: pitch * ny rounded up to 64, plus a
- * 256 KiB + 256 B gap for planes of 16 MiB or more (it spreads the 18 concurrent
- * streams over the HBM channel interleave). */
+/* Elements from one direction plane to the next: pitch * ny rounded up to 64. */
 int64_t ddf_plane_stride(const ddf_params *p);
 /* Bytes of one lattice's populations: 9 planes of ddf_plane_stride storage elements.
  * The caller allocates two such buffers (f and g). */
