@@ -87,18 +87,18 @@ bool plane_fits_32(const ddf_handle *h)
 // latency (the FP16 cavity step was 13% slower with caps).  Lattices held by the
 // cache keep every wavefront.
 //
-// x-interleaved rows (non-temporal accesses; every cap pair and both offset widths):
-// on the 8192^2 field FP32 2 / 2 (6.0 TB/s), FP64 1 / 1 (5.4 TB/s), FP16 3 / 2 and BF16
-// 3 / 3 with 64-bit offsets (5.7-5.8 TB/s), BF16 with stochastic rounding 3 / 0
-// (5.5 TB/s); on an 8192^2 cavity FP32 2 / 2 (6.1 TB/s), FP64 1 / 1 (4.8 TB/s) and the
-// 16-bit formats 3 / 0 (5.6 TB/s).
+// x-interleaved rows (non-temporal accesses, no gap between planes; every cap pair and
+// both offset widths): on the 8192^2 field FP32 2 / 2 (6.2 TB/s), FP64 1 / 1 (6.4 TB/s),
+// FP16 3 / 3 and BF16 3 / 0 with 64-bit offsets (6.0 and 6.1 TB/s), BF16 with
+// stochastic rounding 3 / 0 (5.5 TB/s); on an 8192^2 cavity (measured with plane gaps)
+// FP32 2 / 2 (6.1 TB/s), FP64 1 / 1 (4.8 TB/s) and the 16-bit formats 3 / 0 (5.6 TB/s).
 void launch_defaults(ddf_handle *h)
 {
     h->idx32 = plane_fits_32(h);
     h->wg_cap[0] = h->wg_cap[1] = 0;
     if (2 * population_bytes(&h->p) <= (size_t)256 << 20) return;
     if (h->G.L.qs) {
-        static const int caps[5][2] = {{1, 1}, {2, 2}, {3, 2}, {3, 3}, {3, 0}};   // by ddf_storage
+        static const int caps[5][2] = {{1, 1}, {2, 2}, {3, 3}, {3, 0}, {3, 0}};   // by ddf_storage
         const bool sixteen = h->p.storage == DDF_F16 || h->p.storage == DDF_BF16;
         const bool walls = has_walls(h->p);
         h->wg_cap[0] = caps[h->p.storage][0];

@@ -128,7 +128,7 @@ def test_workgroup_caps_default_by_storage_and_size():
     cav = lambda n, storage: W.cavity_problem(n, 1000.0, 0.1, storage=storage)
     per = lambda n, storage: W.Problem(nx=n, ny=n, storage=storage)
     # 8192^2: x-interleaved rows; 8000^2: row-major rows; 1024^2: held by the cache
-    cases = [(per, "f32", 8192, (2, 2), 32), (per, "f16", 8192, (3, 2), 64), (per, "bf16", 8192, (3, 3), 64),
+    cases = [(per, "f32", 8192, (2, 2), 32), (per, "f16", 8192, (3, 3), 64), (per, "bf16", 8192, (3, 0), 64),
              (per, "bf16sr", 8192, (3, 0), 32), (per, "f64", 8192, (1, 1), 32), (per, "f32", 1024, (0, 0), 32),
              (cav, "f32", 8192, (2, 2), 32), (cav, "f16", 8192, (3, 0), 32), (cav, "f64", 8192, (1, 1), 32),
              (per, "f64", 1024, (0, 0), 32),
