@@ -2,6 +2,7 @@
 
 Usage (each database from its own rocprofv3 run; see profiles/*.md for the commands):
   python -m paper_1908_06742_amd.profiling trace <run_results.db>
+  python -m paper_1908_06742_amd.profiling sequence <run_results.db> --marker k_adam
   python -m paper_1908_06742_amd.profiling counters <fetch.db> <write.db> <copy_fetch.db> <copy_write.db> \
       --kernel k_step --nodes N --bytes-per-node B --tile-width T --out profiles/<name>_counters.json
 
@@ -81,6 +82,23 @@ def cmd_counters(args):
         print(f"wrote {args.out}")
 
 
+def cmd_sequence(args):
+    """The dispatches between the last two complete launches of a marker kernel (one
+    training iteration between two optimizer steps, say): duration of each, their sum
+    and the span from the end of the first marker to the end of the second."""
+    con = sqlite3.connect(args.db)
+    rows = con.execute("select name, start, end from kernels order by start").fetchall()
+    marks = [i for i, r in enumerate(rows) if args.marker in r[0]]
+    if len(marks) < 3:
+        sys.exit(f"fewer than three launches of {args.marker!r}")
+    i0, i1 = marks[-3], marks[-2]   # the last marker may close a shorter, different phase
+    busy = 0.0
+    for name, start, end in rows[i0 + 1:i1 + 1]:
+        busy += (end - start) / 1e3
+        print(f"{(end - start) / 1e3:9.1f} us  {short(name, 80)}")
+    print(f"{i1 - i0} dispatches, busy {busy:.1f} us, span {(rows[i1][2] - rows[i0][2]) / 1e3:.1f} us")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -99,8 +117,11 @@ def main(argv=None):
     c.add_argument("--bytes-per-node", type=int, required=True)
     c.add_argument("--tile-width", type=int, required=True, help="tile width of the profiled lattice")
     c.add_argument("--out")
+    q = sub.add_parser("sequence")
+    q.add_argument("db")
+    q.add_argument("--marker", default="k_adam", help="kernel whose consecutive launches bound the sequence")
     args = ap.parse_args(argv)
-    {"trace": cmd_trace, "counters": cmd_counters}[args.cmd](args)
+    {"trace": cmd_trace, "counters": cmd_counters, "sequence": cmd_sequence}[args.cmd](args)
 
 
 if __name__ == "__main__":
