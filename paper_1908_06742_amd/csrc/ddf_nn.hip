@@ -419,30 +419,42 @@ __device__ __forceinline__ bf16x8 tr_operand(const __bf16 *p, int row_stride)
     return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
 }
 
-// LDS-staged weight gradient.  A workgroup of three wavefronts, one per kernel row
-// (dy = -1, 0, 1), walks a run of pixel blocks; a block is PB consecutive pixels of one
-// image row.  Per block it stages with 16-byte loads the output gradient dout[PB][32 CO_T]
-// and the three input rows in[y-1 .. y+1][x0-1 .. x0+PB] (zero outside the image); then
-// each wavefront contracts over the block's pixels for its three taps (dx = -1, 0, 1)
-// and its CO_T x CI_T output tiles of 32 x 32, so each staged value feeds several MFMAs.
-// The contraction runs over pixels, which NHWC keeps strided: operands come out of the
+// LDS-staged weight gradient.  A sub-group of three wavefronts, one per kernel row
+// (dy = -1, 0, 1), walks pixel blocks; a block is PB consecutive pixels of one image row.
+// Per block it stages with 16-byte loads the output gradient dout[PB][32 CO_T] and the
+// three input rows in[y-1 .. y+1][x0-1 .. x0+PB] (zero outside the image); then each
+// wavefront contracts over the block's pixels for its three taps (dx = -1, 0, 1) and its
+// CO_T x CI_T output tiles of 32 x 32, so each staged value feeds several MFMAs.  The
+// contraction runs over pixels, which NHWC keeps strided: operands come out of the
 // [pixel][channel] tiles by transpose reads (tr_operand); rows are padded by 8 elements.
-// part[chunk * cstride + (tap Cout + co) Cin + ci] receives the chunk's sums (tap =
-// 3 (dy + 1) + dx + 1).  The workgroups of the first input-channel tile also sum the
-// staged output gradient over the chunk's pixels into bpart[chunk * cstride + co] (bias
-// gradient), in a fixed order.
-template <int PB, int CO_T, int CI_T>
-__global__ __launch_bounds__(192) void k_wgrad_lds(const __bf16 *__restrict__ in, int N, int H, int W, int Cin,
-                                                   int in_cs, int in_co, const __bf16 *__restrict__ dout, int Cout,
-                                                   int d_cs, int blocks_per_chunk, float *__restrict__ part,
-                                                   float *__restrict__ bpart, int64_t cstride)
+// A workgroup holds SUB sub-groups with their own staging buffers; sub-group s takes
+// blocks b0 + s, b0 + s + SUB, ... of the workgroup's chunk, and at the end the sub-groups'
+// accumulators are added in LDS in the order s = 0, 1, ..., so a chunk writes one set
+// of partials for SUB times the pixels (the partials are written once and read once by
+// the split-K sum).  part[chunk * cstride + (tap Cout + co) Cin + ci] receives the
+// chunk's sums (tap = 3 (dy + 1) + dx + 1).  The workgroups of the first input-channel
+// tile also sum the staged output gradient over the chunk's pixels into
+// bpart[chunk * cstride + co] (bias gradient), in a fixed order.
+template <int PB, int CO_T, int CI_T, int SUB = 1>
+__global__ __launch_bounds__(192 * SUB) void k_wgrad_lds(const __bf16 *__restrict__ in, int N, int H, int W, int Cin,
+                                                         int in_cs, int in_co, const __bf16 *__restrict__ dout, int Cout,
+                                                         int d_cs, int blocks_per_chunk, float *__restrict__ part,
+                                                         float *__restrict__ bpart, int64_t cstride)
 {
     constexpr int XS = 32 * CI_T + 8;
     constexpr int DS = 32 * CO_T + 8;
-    __shared__ __attribute__((aligned(16))) __bf16 xs[3][PB + 2][XS];
-    __shared__ __attribute__((aligned(16))) __bf16 ds[PB][DS];
-    __shared__ float bred[192][8];
-    const int tid = threadIdx.x, lane = tid & 63, r = tid >> 6;
+    constexpr int NT = 192 * SUB;
+    constexpr size_t XB = (size_t)SUB * 3 * (PB + 2) * XS * 2, DB = (size_t)SUB * PB * DS * 2;
+    constexpr size_t RB = SUB > 1 ? (size_t)192 * 16 * CO_T * CI_T * 4 : 0;   // one kernel column of a sub-group
+    constexpr size_t SB = XB + DB > RB ? XB + DB : RB;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[SB];
+    __shared__ float bred[NT][8];
+    typedef __bf16 XRow[PB + 2][XS];
+    typedef __bf16 DRow[DS];
+    const int tid = threadIdx.x, sub = tid / 192, t = tid - 192 * sub;
+    const int lane = t & 63, r = t >> 6;
+    XRow *xs = (XRow *)smem + 3 * sub;                   // this sub-group's three input rows
+    DRow *ds = (DRow *)(smem + XB) + PB * sub;           // and output-gradient block
     const int m = lane & 31, half = lane >> 5;
     const int tiles_ci = Cin / (32 * CI_T);
     const int ci0 = (blockIdx.x % tiles_ci) * 32 * CI_T, co0 = (blockIdx.x / tiles_ci) * 32 * CO_T;
@@ -467,70 +479,75 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(const __bf16 *__restrict__ in
             for (int b = 0; b < CI_T; ++b)
 #pragma unroll
                 for (int j = 0; j < 16; ++j) acc[dx][a][b][j] = 0.0f;
-    // Staging is software-pipelined: the global loads of block blk + 1 are issued into
-    // registers before the MFMAs of block blk and written to LDS after them.
+    // Staging is software-pipelined: the global loads of a sub-group's next block are
+    // issued into registers before the MFMAs of its current block and written to LDS
+    // after them.  Every sub-group makes the same number of turns (blocks past the chunk
+    // stage zeros), so the workgroup's barriers match.
     constexpr int XV = 3 * (PB + 2) * 4 * CI_T;   // 16-byte input vectors per block
     constexpr int DV = PB * 4 * CO_T;             // 16-byte output-gradient vectors per block
     constexpr int NXV = (XV + 191) / 192, NDV = (DV + 191) / 192;
     bf16x8 xr[NXV], dr[NDV];
     auto fetch = [&](int64_t blk) {
+        const bool ok = blk < b1;
         const int x0 = (int)(blk % bpr) * PB;
         const int64_t row = blk / bpr;   // n * H + y
         const int y = (int)(row % H);
 #pragma unroll
         for (int i = 0; i < NXV; ++i) {
-            const int v = tid + 192 * i;
+            const int v = t + 192 * i;
             const int c8 = v % (4 * CI_T), q = v / (4 * CI_T);
             const int px = q % (PB + 2), rr = q / (PB + 2);
             const int yy = y + rr - 1, xx = x0 + px - 1;
             xr[i] = zero8();
-            if (v < XV && yy >= 0 && yy < H && xx >= 0 && xx < W)
+            if (ok && v < XV && yy >= 0 && yy < H && xx >= 0 && xx < W)
                 xr[i] = load8(in + ((row + rr - 1) * W + xx) * in_cs + in_co + ci0 + 8 * c8);
         }
 #pragma unroll
         for (int i = 0; i < NDV; ++i) {
-            const int v = tid + 192 * i;
+            const int v = t + 192 * i;
             const int c8 = v % (4 * CO_T), px = v / (4 * CO_T);
             dr[i] = zero8();
-            if (v < DV) dr[i] = load8(dout + (row * W + x0 + px) * d_cs + co0 + 8 * c8);
+            if (ok && v < DV) dr[i] = load8(dout + (row * W + x0 + px) * d_cs + co0 + 8 * c8);
         }
     };
-    if (b0 < b1) fetch(b0);
-    for (int64_t blk = b0; blk < b1; ++blk) {
+    const int64_t turns = (b1 - b0 + SUB - 1) / SUB;
+    if (turns > 0) fetch(b0 + sub);
+    for (int64_t k = 0; k < turns; ++k) {
+        const int64_t blk = b0 + k * SUB + sub;
 #pragma unroll
         for (int i = 0; i < NXV; ++i) {
-            const int v = tid + 192 * i;
+            const int v = t + 192 * i;
             const int c8 = v % (4 * CI_T), q = v / (4 * CI_T);
             if (v < XV) *(bf16x8 *)&xs[q / (PB + 2)][q % (PB + 2)][8 * c8] = xr[i];
         }
         // 192 is a multiple of 4 CO_T: a thread keeps one group of 8 channels
 #pragma unroll
         for (int i = 0; i < NDV; ++i) {
-            const int v = tid + 192 * i;
+            const int v = t + 192 * i;
             const int c8 = v % (4 * CO_T), px = v / (4 * CO_T);
             if (v < DV) {
                 *(bf16x8 *)&ds[px][8 * c8] = dr[i];
-                if (bias) {
+                if (bias) {   // blocks past the chunk staged zeros
 #pragma unroll
                     for (int j = 0; j < 8; ++j) bsum[j] += (float)dr[i][j];
                 }
             }
         }
         __syncthreads();
-        if (blk + 1 < b1) fetch(blk + 1);
+        if (k + 1 < turns) fetch(blk + SUB);
 #pragma unroll
         for (int k0 = 0; k0 < PB; k0 += 16) {
             bf16x8 a[CO_T];
 #pragma unroll
-            for (int t = 0; t < CO_T; ++t) a[t] = tr_operand(&ds[k0 + tr_row][32 * t + tr_col], DS);
+            for (int tt = 0; tt < CO_T; ++tt) a[tt] = tr_operand(&ds[k0 + tr_row][32 * tt + tr_col], DS);
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
 #pragma unroll
                 for (int u = 0; u < CI_T; ++u) {
                     const bf16x8 b = tr_operand(&xs[r][k0 + tr_row + dx][32 * u + tr_col], XS);
 #pragma unroll
-                    for (int t = 0; t < CO_T; ++t)
-                        acc[dx][t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[t], b, acc[dx][t][u], 0, 0, 0);
+                    for (int tt = 0; tt < CO_T; ++tt)
+                        acc[dx][tt][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[tt], b, acc[dx][tt][u], 0, 0, 0);
                 }
             }
         }
@@ -542,23 +559,52 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(const __bf16 *__restrict__ in
         __syncthreads();
         if (tid < 32 * CO_T) {
             const int c8 = tid >> 3, i = tid & 7;
-            float t = 0.0f;
-            for (int u = c8; u < 192; u += 4 * CO_T) t += bred[u][i];
-            bpart[(int64_t)ck * cstride + co0 + 8 * c8 + i] = t;
+            float s8 = 0.0f;
+            for (int u = c8; u < NT; u += 4 * CO_T) s8 += bred[u][i];
+            bpart[(int64_t)ck * cstride + co0 + 8 * c8 + i] = s8;
         }
     }
+    if constexpr (SUB > 1) {
+        // sub-group 0 adds the others' accumulators, one kernel column at a time, in the
+        // order 1, 2, ...: thread t of sub-group s passes its values through red[t][...]
+        float *red = (float *)smem;
 #pragma unroll
-    for (int dx = 0; dx < 3; ++dx) {
-        float *o = part + (int64_t)ck * cstride + ((int64_t)(3 * r + dx) * Cout) * Cin;
+        for (int dx = 0; dx < 3; ++dx)
+            for (int s2 = 1; s2 < SUB; ++s2) {
+                __syncthreads();   // the staging buffers (or the previous column) are free
+                if (sub == s2) {
 #pragma unroll
-        for (int t = 0; t < CO_T; ++t)
+                    for (int tt = 0; tt < CO_T; ++tt)
 #pragma unroll
-            for (int u = 0; u < CI_T; ++u)
+                        for (int u = 0; u < CI_T; ++u)
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    const int co = co0 + 32 * t + 8 * (j >> 2) + 4 * half + (j & 3);
-                    o[(int64_t)co * Cin + ci0 + 32 * u + m] = acc[dx][t][u][j];
+                            for (int j = 0; j < 16; ++j) red[((tt * CI_T + u) * 16 + j) * 192 + t] = acc[dx][tt][u][j];
                 }
+                __syncthreads();
+                if (sub == 0) {
+#pragma unroll
+                    for (int tt = 0; tt < CO_T; ++tt)
+#pragma unroll
+                        for (int u = 0; u < CI_T; ++u)
+#pragma unroll
+                            for (int j = 0; j < 16; ++j) acc[dx][tt][u][j] += red[((tt * CI_T + u) * 16 + j) * 192 + t];
+                }
+            }
+    }
+    if (sub == 0) {
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            float *o = part + (int64_t)ck * cstride + ((int64_t)(3 * r + dx) * Cout) * Cin;
+#pragma unroll
+            for (int tt = 0; tt < CO_T; ++tt)
+#pragma unroll
+                for (int u = 0; u < CI_T; ++u)
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        const int co = co0 + 32 * tt + 8 * (j >> 2) + 4 * half + (j & 3);
+                        o[(int64_t)co * Cin + ci0 + 32 * u + m] = acc[dx][tt][u][j];
+                    }
+        }
     }
 }
 
@@ -1100,6 +1146,7 @@ namespace {
 struct WgradPlan {
     bool lds;              // LDS-staged kernel (rows of W % 16 == 0 pixels)
     int pb, co_t, ci_t;    // its pixel block and tile multiples
+    int sub;               // three-wavefront sub-groups per workgroup
     int64_t nchunk;        // split-K chunks (partials)
     int64_t per_chunk;     // pixel blocks (LDS kernel) or pixels (gather kernel) per chunk
 };
@@ -1118,12 +1165,18 @@ WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout)
         // SIMD) measured slower at every layer size of the surrogate network.
         P.co_t = npix > 32768 && Cout % 64 == 0 ? 2 : 1;
         P.ci_t = 1;
+        // Four sub-groups per workgroup (their accumulators added in LDS, a quarter of the
+        // partials) where one 32-channel output tile meets several input tiles on a large
+        // image: the surrogate's 96 -> 32 at 8 x 256^2, 103 -> 86 us.  Elsewhere they
+        // measured level or slower: the pixel split's parallelism matters more than the
+        // partials' bytes.
+        P.sub = P.pb == 64 && Cout == 32 && Cin >= 64 && npix >= 262144 ? 4 : 1;
         const int64_t groups = (int64_t)(Cin / (32 * P.ci_t)) * (Cout / (32 * P.co_t));
         const int64_t nblocks = npix / P.pb;
-        // about kWgradGroups workgroups; half as many, with twice the pixels each, where
-        // several channel tiles split a large image (the surrogate's 64 -> 64, 192 -> 64 at
-        // 8 x 128^2 and 96 -> 32 at 8 x 256^2: 8-22% faster)
-        const int64_t target = groups >= 2 && npix >= 131072 ? kWgradGroups / 2 : kWgradGroups;
+        // about kWgradGroups three-wavefront sub-groups; half as many, with twice the pixels
+        // each, where several channel tiles split a large image (the surrogate's 64 -> 64
+        // and 192 -> 64 at 8 x 128^2: 8-22% faster)
+        const int64_t target = (P.sub == 1 && groups >= 2 && npix >= 131072 ? kWgradGroups / 2 : kWgradGroups) / P.sub;
         // bytes read: each workgroup stages its input-channel and output-channel slices
         const double reads = 2.0 * (double)npix *
                              ((double)Cin * (Cout / (32 * P.co_t)) + (double)Cout * (Cin / (32 * P.ci_t)));
@@ -1132,6 +1185,7 @@ WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout)
         int64_t nchunk = (target + groups - 1) / groups;
         nchunk = std::max<int64_t>(1, std::min<int64_t>({nchunk, cap, nblocks}));
         P.per_chunk = (nblocks + nchunk - 1) / nchunk;
+        P.per_chunk = (P.per_chunk + P.sub - 1) / P.sub * P.sub;
         P.nchunk = (nblocks + P.per_chunk - 1) / P.per_chunk;
     } else {
         // gather kernel: about kWgradWaves single-wave workgroups, chunks of >= 256 pixels
@@ -1153,11 +1207,17 @@ int launch_wgrad_lds(const WgradPlan &P, const __bf16 *in, int N, int H, int W, 
 {
     const dim3 grid((unsigned)((Cin / (32 * P.ci_t)) * (Cout / (32 * P.co_t))), (unsigned)P.nchunk);
     const int bpc = (int)P.per_chunk;
-#define DDF_WGRAD_LAUNCH(CO, CI)                                                                                   \
-    hipLaunchKernelGGL((k_wgrad_lds<PB, CO, CI>), grid, dim3(192), 0, st, in, N, H, W, Cin, in_cs, in_co, dout, Cout, \
-                       d_cs, bpc, part, bpart, cstride)
-    if (P.co_t == 2) DDF_WGRAD_LAUNCH(2, 1);
-    else DDF_WGRAD_LAUNCH(1, 1);
+#define DDF_WGRAD_LAUNCH(CO, CI, S)                                                                                \
+    hipLaunchKernelGGL((k_wgrad_lds<PB, CO, CI, S>), grid, dim3(192 * S), 0, st, in, N, H, W, Cin, in_cs, in_co, dout, \
+                       Cout, d_cs, bpc, part, bpart, cstride)
+    if (P.co_t == 2) {
+        DDF_WGRAD_LAUNCH(2, 1, 1);
+    } else if constexpr (PB == 64) {
+        if (P.sub == 4) DDF_WGRAD_LAUNCH(1, 1, 4);
+        else DDF_WGRAD_LAUNCH(1, 1, 1);
+    } else {
+        DDF_WGRAD_LAUNCH(1, 1, 1);
+    }
 #undef DDF_WGRAD_LAUNCH
     return DDF_OK;
 }

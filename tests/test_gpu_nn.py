@@ -520,6 +520,36 @@ def test_conv3x3_lds_configs(B, H, W, Cin, Cout, cs_in, co_in, cs_out, co_out, a
     assert np.array_equal(got[..., untouched], out0q[..., untouched])
 
 
+def test_weight_gradient_with_sub_groups_and_a_ragged_last_chunk():
+    # 64 -> 32 channels on 2 x 683 x 192 pixels: four sub-groups per workgroup, whose
+    # accumulators are added in LDS; the last chunk's 6 blocks leave two sub-groups a turn
+    # of zeros.  Every entry against the float64 sum over all pixels.
+    B, H, W, Cin, Cout = 2, 683, 192, 64, 32
+    r = np.random.default_rng(77)
+    xt, x = bf(r.standard_normal((B, H, W, Cin)))
+    dyt, dy = bf(r.standard_normal((B, H, W, Cout)))
+    chunk = C.c_int32()
+    nbytes = L.lib().ddf_nn_wgrad_workspace_bytes(B, H, W, Cin, Cout, C.byref(chunk))
+    assert (B * H * W // 64) % (chunk.value // 64) == 6
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=DEV)
+    dw = torch.empty(9 * Cout * Cin, dtype=torch.float32, device=DEV)
+    db = torch.empty(Cout, dtype=torch.float32, device=DEV)
+    L.check(L.lib().ddf_nn_conv3x3_wgrad(p(xt), B, H, W, Cin, Cin, 0, p(dyt), Cout, Cout, p(dw), p(db), 0, p(ws), s0()))
+    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (0, 0)))
+    d2 = dy.reshape(-1, Cout)
+    ref = np.empty((9, Cout, Cin))
+    mag = np.empty((9, Cout, Cin))
+    for tap in range(9):
+        ky, kx = divmod(tap, 3)
+        xs = xp[:, ky:ky + H, kx:kx + W, :].reshape(-1, Cin)
+        ref[tap] = d2.T @ xs
+        mag[tap] = np.abs(d2).T @ np.abs(xs)
+    got = dw.cpu().numpy().reshape(9, Cout, Cin)
+    assert np.max(np.abs(got - ref) / mag) < 2e-5     # FP32 sums of exact BF16 products
+    gb = db.cpu().numpy()
+    assert np.max(np.abs(gb - d2.sum(axis=0)) / np.abs(d2).sum(axis=0)) < 2e-5
+
+
 @pytest.mark.parametrize("H,Cin,Cout", [
     (256, 32, 32),     # 32 -> 32 at 256^2: 256-pixel convolution segments, single-tile weight gradient
     (256, 96, 32),     # the level-0 decoder input: 128-pixel segments
