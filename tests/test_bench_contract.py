@@ -1,0 +1,54 @@
+"""bench.py pieces that need no GPU: the one-GPU refusal, the counter-summary lookup
+behind `roofline.traffic`, and the U-Net FLOP count behind its TFLOP/s."""
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_traffic_comes_only_from_counters_of_the_current_kernel(tmp_path, monkeypatch):
+    f = tmp_path / "counters.json"
+    rec = {"kernel_hash": bench.kernel_hash(), "nodes": 64, "tile_width": 128, "bytes_per_launch": 123.0}
+    f.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "COUNTERS_FILE", str(f))
+    assert bench.measured_traffic(64, 128) == 123.0
+    assert bench.measured_traffic(64, 64) is None            # another tile width
+    assert bench.measured_traffic(65, 128) is None           # another lattice
+    f.write_text(json.dumps(dict(rec, kernel_hash="0" * 16)))
+    assert bench.measured_traffic(64, 128) is None           # the kernel changed since
+    monkeypatch.setattr(bench, "COUNTERS_FILE", str(tmp_path / "missing.json"))
+    assert bench.measured_traffic(64, 128) is None
+
+
+def test_kernel_hash_covers_every_kernel_source(tmp_path, monkeypatch):
+    srcs = []
+    for i in range(3):
+        p = tmp_path / f"s{i}.hip"
+        p.write_text(f"// {i}\n")
+        srcs.append(str(p))
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", srcs)
+    h0 = bench.kernel_hash()
+    assert len(h0) == 16 and int(h0, 16) >= 0
+    (tmp_path / "s2.hip").write_text("// changed\n")
+    assert bench.kernel_hash() != h0
+
+
+def test_unet_flop_count():
+    # 2 x 9 x Cin x Cout per output pixel over the 15 layers (channels padded to 32, the
+    # 5 input channels to 32), at 256^2: 23.56 GFLOP forward, and three times that minus
+    # the first layer's data gradient for a training step
+    fwd, train = bench.unet_flops_per_sample()
+    first = 2.0 * 9 * 32 * 32 * 256 * 256
+    assert abs(fwd - 23.56e9) < 0.01e9
+    assert train == 3 * fwd - first
+    assert abs(train - 69.46e9) < 0.01e9
