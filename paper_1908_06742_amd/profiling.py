@@ -84,19 +84,25 @@ def cmd_counters(args):
 
 def cmd_sequence(args):
     """The dispatches between the last two complete launches of a marker kernel (one
-    training iteration between two optimizer steps, say): duration of each, their sum
-    and the span from the end of the first marker to the end of the second."""
+    training iteration between two optimizer steps, say): duration of each, their sum,
+    the time the GPU runs at least one of them (kernels on several streams overlap) and
+    the span from the end of the first marker to the end of the second."""
     con = sqlite3.connect(args.db)
     rows = con.execute("select name, start, end from kernels order by start").fetchall()
     marks = [i for i, r in enumerate(rows) if args.marker in r[0]]
     if len(marks) < 3:
         sys.exit(f"fewer than three launches of {args.marker!r}")
     i0, i1 = marks[-3], marks[-2]   # the last marker may close a shorter, different phase
-    busy = 0.0
+    total = busy = 0.0
+    reach = rows[i0][2]             # union of the intervals, swept in start order
     for name, start, end in rows[i0 + 1:i1 + 1]:
-        busy += (end - start) / 1e3
-        print(f"{(end - start) / 1e3:9.1f} us  {short(name, 80)}")
-    print(f"{i1 - i0} dispatches, busy {busy:.1f} us, span {(rows[i1][2] - rows[i0][2]) / 1e3:.1f} us")
+        total += (end - start) / 1e3
+        busy += max(0, end - max(start, reach)) / 1e3
+        mark = f"  (overlaps {(min(end, reach) - start) / 1e3:.1f} us)" if start < reach else ""
+        reach = max(reach, end)
+        print(f"{(end - start) / 1e3:9.1f} us  {short(name, 80)}{mark}")
+    print(f"{i1 - i0} dispatches, kernel time {total:.1f} us, busy {busy:.1f} us, "
+          f"span {(rows[i1][2] - rows[i0][2]) / 1e3:.1f} us")
 
 
 def main(argv=None):

@@ -53,10 +53,13 @@ def _pad(c):
 
 
 class UNet:
-    def __init__(self, base=32, levels=4, device="cuda", seed=0, stream=None):
+    def __init__(self, base=32, levels=4, device="cuda", seed=0, stream=None, overlap_wgrad=True):
         self.base, self.levels = base, levels
         self.device = torch.device(device)
         self.stream = stream
+        # weight gradients on a second stream, overlapped with the data-gradient chain
+        self.overlap_wgrad = overlap_wgrad
+        self._side = None
         self.table = layer_table(base, levels)
         self.ch = [base * 2 ** k for k in range(levels)]
         # flat FP32 parameter layout: per layer w[9][cout_p][cin_p] then b[cout_p], channel
@@ -107,9 +110,39 @@ class UNet:
         w0, b0 = self.off[name]
         return C.c_void_p(t.data_ptr() + 4 * (b0 if bias else w0))
 
+    def _main(self):
+        return self.stream if self.stream is not None else torch.cuda.current_stream(self.device)
+
     def _s(self):
-        s = self.stream if self.stream is not None else torch.cuda.current_stream()
-        return C.c_void_p(s.cuda_stream)
+        return C.c_void_p(self._main().cuda_stream)
+
+    def _wgrad_stream(self):
+        """Stream of the next weight-gradient launch.  With overlap, the side stream first
+        waits for everything queued so far on the main stream (the layer's output gradient
+        and, for skip connections, the pooling adjoint accumulated into it); the weight
+        gradients run in order on that one stream, so they share the split-K workspace.
+        Returns a function that launches on it."""
+        if not self.overlap_wgrad:
+            s = self._s()
+            return lambda launch: launch(s)
+        if self._side is None:
+            self._side = torch.cuda.Stream(device=self.device)
+        ev = torch.cuda.Event()
+        ev.record(self._main())
+        side = self._side
+
+        def run(launch):
+            side.wait_event(ev)
+            launch(C.c_void_p(side.cuda_stream))
+        return run
+
+    def _join_wgrad(self):
+        """The main stream waits for the queued weight gradients (before Adam, and before
+        a later forward overwrites the activations they read)."""
+        if self.overlap_wgrad and self._side is not None:
+            ev = torch.cuda.Event()
+            ev.record(self._side)
+            self._main().wait_event(ev)
 
     def cast(self):
         """BF16 forward and data-gradient copies of every layer, one launch per 32 layers."""
@@ -265,13 +298,15 @@ class UNet:
         dyt, dcs, dco = (self.G[name], cop, 0) if dy is None else dy
         # the weight gradient takes the output gradient's channel offset in its pointer
         # (bf16 elements, offsets multiples of 8: 16-byte aligned)
-        L.check(lib.ddf_nn_conv3x3_wgrad(_p(src), B, h, w, cip, src_cs, 0, C.c_void_p(dyt.data_ptr() + 2 * dco), cop,
-                                         dcs, self._wptr(self.g, name), self._wptr(self.g, name, bias=True), 0,
-                                         _p(self.ws), s))
+        wgrad = self._wgrad_stream()   # ordered after the producers of dY, before the data gradient
         if dsrc is not None:
+            # the data gradient first: the rest of the backward chain waits for it
             mask = _p(src) if src_relu else None
             L.check(lib.ddf_nn_conv3x3(_p(dyt), B, h, w, cop, dcs, dco, _p(self.wd[name]), None, _p(dsrc), cip, cip, 0,
                                        0, int(acc), mask, src_cs, 0, s))
+        wgrad(lambda st: L.check(lib.ddf_nn_conv3x3_wgrad(
+            _p(src), B, h, w, cip, src_cs, 0, C.c_void_p(dyt.data_ptr() + 2 * dco), cop, dcs, self._wptr(self.g, name),
+            self._wptr(self.g, name, bias=True), 0, _p(self.ws), st)))
 
     def backward(self, B, H, W):
         """Needs G['head'] = dLoss/dOut; fills self.g with every parameter's gradient."""
@@ -303,6 +338,7 @@ class UNet:
                                              _p(ak), 1, s))
             else:
                 self._conv_back("enc0a", self.x, CIN_P, None, 0, B, hh, ww)
+        self._join_wgrad()
 
     # ---------------------------------------------------------------- training
     def loss_and_grad(self, target, B, H, W, weights=(1.0, 1.0, 1.0, 1.0)):

@@ -391,6 +391,25 @@ def test_training_reduces_loss():
     assert losses[-1] < 0.2 * losses[0], (losses[0], losses[-1])
 
 
+@pytest.mark.parametrize("B,H", [(2, 128), (8, 256)])
+def test_weight_gradients_on_a_side_stream_match_one_stream(B, H):
+    # the weight gradients overlap the data-gradient chain on a second stream; the
+    # kernels are the same, so three training steps (Adam and the next forward wait
+    # for them) must give bit-identical gradients and weights
+    W = H
+    nets = [UNet(base=32, levels=4, device=DEV, seed=5, overlap_wgrad=ov) for ov in (False, True)]
+    g = torch.Generator(device=DEV).manual_seed(B)
+    re = 100.0 + 4900.0 * torch.rand(B, device=DEV, generator=g)
+    u = 0.05 + 0.05 * torch.rand(B, device=DEV, generator=g)
+    tgt = torch.randn(B * H * W * 4, device=DEV, generator=g)
+    for it in range(3):
+        losses = [net.train_step(re, u, tgt, H, W, lr=1e-3).item() for net in nets]
+        assert losses[0] == losses[1], (it, losses)
+        assert torch.equal(nets[0].g, nets[1].g), it
+        assert torch.equal(nets[0].w, nets[1].w), it
+    assert nets[1]._side is not None and nets[0]._side is None
+
+
 @pytest.mark.parametrize("C,off", [(32, 0), (13, 0), (32, 2)])   # 16-byte stores; single stores (C % 8, unaligned)
 def test_cavity_input_channels(C, off):
     B, H, W = 2, 16, 24

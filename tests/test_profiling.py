@@ -37,9 +37,26 @@ def test_kernel_stats_and_sequence(tmp_path, capsys):
     P.main(["sequence", db, "--marker", "k_adam"])
     out = capsys.readouterr().out.splitlines()
     # between the second and third adam: conv, wgrad, adam; busy 35 us; span = 3 gaps + 35 us
-    assert out[-1] == "3 dispatches, busy 35.0 us, span 38.0 us"
+    assert out[-1] == "3 dispatches, kernel time 35.0 us, busy 35.0 us, span 38.0 us"
     with pytest.raises(SystemExit):
         P.main(["sequence", db, "--marker", "k_missing"])
+
+
+def test_sequence_counts_overlapping_kernels_once(tmp_path, capsys):
+    # per iteration: conv 0-10, wgrad 5-25 (second stream), sum 12-14 (inside wgrad),
+    # adam 26-31; the next iteration starts at 40
+    db = str(tmp_path / "o.db")
+    rows = []
+    for it in range(4):
+        t = 40_000 * it
+        rows += [("k_conv", t, t + 10_000), ("k_wgrad", t + 5_000, t + 25_000), ("k_sum", t + 12_000, t + 14_000),
+                 ("k_adam", t + 26_000, t + 31_000)]
+    _kernels_db(db, rows)
+    P.main(["sequence", db, "--marker", "k_adam"])
+    out = capsys.readouterr().out.splitlines()
+    assert out[1].endswith("(overlaps 5.0 us)") and out[2].endswith("(overlaps 2.0 us)") and "overlaps" not in out[0]
+    # kernel time 10 + 20 + 2 + 5 = 37; busy 0-25 and 26-31 = 30; span 31 - (-9) = 40
+    assert out[-1] == "4 dispatches, kernel time 37.0 us, busy 30.0 us, span 40.0 us"
 
 
 def test_counters_scale_by_the_copy_calibration(tmp_path, capsys):
