@@ -758,34 +758,50 @@ __global__ void k_relu_bwd8(__bf16 *__restrict__ g, const __bf16 *__restrict__ a
     store8(g + 8 * i, gv);
 }
 
-__global__ void k_pool2_8(const __bf16 *__restrict__ in, int N, int H, int W, int C, int in_cs, int ic0,
+// Row grid of the 8-channel resampling kernels: each block covers part of one pixel row
+// (bpr blocks per row, `items` = row width x C / 8 threads' work per row), so the row,
+// and with it the image and y, is uniform per block and a lane derives only its pixel and
+// channel group, by a shift where C / 8 is a power of two (64-bit index division per lane
+// made these kernels instruction-bound).
+struct RowGrid {
+    int bpr, items, C8, c8s;   // c8s = log2(C / 8), or -1
+};
+
+__device__ __forceinline__ bool row_item(const RowGrid &g, int &row, int &x, int &c)
+{
+    row = (int)blockIdx.x / g.bpr;
+    const int j = ((int)blockIdx.x - row * g.bpr) * (int)blockDim.x + (int)threadIdx.x;
+    if (j >= g.items) return false;
+    x = g.c8s >= 0 ? j >> g.c8s : j / g.C8;
+    c = 8 * (j - x * g.C8);
+    return true;
+}
+
+// rows = N x h output rows of w pixels
+__global__ void k_pool2_8(const __bf16 *__restrict__ in, const RowGrid g, int H, int W, int C, int in_cs, int ic0,
                           __bf16 *__restrict__ out)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int h = H / 2, w = W / 2, C8 = C / 8;
-    if (i >= (int64_t)N * h * w * C8) return;
-    const int c = 8 * (int)(i % C8);
-    const int64_t q = i / C8;
-    const int xo = q % w, yo = (q / w) % h, n = q / ((int64_t)w * h);
+    int row, xo, c;
+    if (!row_item(g, row, xo, c)) return;
+    const int h = H / 2, w = W / 2;
+    const int n = row / h, yo = row - n * h;
     const __bf16 *b = in + ((int64_t)(n * H + 2 * yo) * W + 2 * xo) * in_cs + ic0 + c;
     const int64_t rs = (int64_t)W * in_cs;
     const bf16x8 a0 = load8(b), a1 = load8(b + in_cs), a2 = load8(b + rs), a3 = load8(b + rs + in_cs);
     bf16x8 r;
 #pragma unroll
     for (int k = 0; k < 8; ++k) r[k] = (__bf16)(0.25f * ((float)a0[k] + (float)a1[k] + (float)a2[k] + (float)a3[k]));
-    store8(out + q * C + c, r);
+    store8(out + ((int64_t)row * w + xo) * C + c, r);
 }
 
-__global__ void k_pool2_bwd8(const __bf16 *__restrict__ dout, int N, int H, int W, int C, __bf16 *__restrict__ din,
-                             int d_cs, int dc0, const __bf16 *__restrict__ mask, int accumulate)
+// rows = N x H input rows of W pixels
+__global__ void k_pool2_bwd8(const __bf16 *__restrict__ dout, const RowGrid g, int H, int W, int C,
+                             __bf16 *__restrict__ din, int d_cs, int dc0, const __bf16 *__restrict__ mask, int accumulate)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int C8 = C / 8;
-    if (i >= (int64_t)N * H * W * C8) return;
-    const int c = 8 * (int)(i % C8);
-    const int64_t q = i / C8;
-    const int x = q % W, y = (q / W) % H, n = q / ((int64_t)W * H);
-    const int64_t e = q * d_cs + dc0 + c;
+    int row, x, c;
+    if (!row_item(g, row, x, c)) return;
+    const int n = row / H, y = row - n * H;
+    const int64_t e = ((int64_t)row * W + x) * d_cs + dc0 + c;
     const bf16x8 d = load8(dout + ((int64_t)(n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c);
     bf16x8 r = accumulate ? load8(din + e) : zero8();
     const bf16x8 mk = mask ? load8(mask + e) : zero8();
@@ -798,27 +814,24 @@ __global__ void k_pool2_bwd8(const __bf16 *__restrict__ dout, int N, int H, int 
     store8(din + e, r);
 }
 
-__global__ void k_up2_8(const __bf16 *__restrict__ in, int N, int h, int w, int C, __bf16 *__restrict__ out,
+// rows = N x 2h output rows of 2w pixels
+__global__ void k_up2_8(const __bf16 *__restrict__ in, const RowGrid g, int h, int w, int C, __bf16 *__restrict__ out,
                         int out_cs, int oc0)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int H = 2 * h, W = 2 * w, C8 = C / 8;
-    if (i >= (int64_t)N * H * W * C8) return;
-    const int c = 8 * (int)(i % C8);
-    const int64_t q = i / C8;
-    const int x = q % W, y = (q / W) % H, n = q / ((int64_t)W * H);
-    store8(out + q * out_cs + oc0 + c, load8(in + ((int64_t)(n * h + y / 2) * w + x / 2) * C + c));
+    int row, x, c;
+    if (!row_item(g, row, x, c)) return;
+    const int H = 2 * h, W = 2 * w;
+    const int n = row / H, y = row - n * H;
+    store8(out + ((int64_t)row * W + x) * out_cs + oc0 + c, load8(in + ((int64_t)(n * h + y / 2) * w + x / 2) * C + c));
 }
 
-__global__ void k_up2_bwd8(const __bf16 *__restrict__ dout, int N, int h, int w, int C, int d_cs, int dc0,
+// rows = N x h output rows of w pixels
+__global__ void k_up2_bwd8(const __bf16 *__restrict__ dout, const RowGrid g, int h, int w, int C, int d_cs, int dc0,
                            __bf16 *__restrict__ din)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int C8 = C / 8;
-    if (i >= (int64_t)N * h * w * C8) return;
-    const int c = 8 * (int)(i % C8);
-    const int64_t q = i / C8;
-    const int x = q % w, y = (q / w) % h, n = q / ((int64_t)w * h);
+    int row, x, c;
+    if (!row_item(g, row, x, c)) return;
+    const int n = row / h, y = row - n * h;
     const int W = 2 * w;
     const int64_t b = ((int64_t)(n * 2 * h + 2 * y) * W + 2 * x);
     const bf16x8 a0 = load8(dout + b * d_cs + dc0 + c), a1 = load8(dout + (b + 1) * d_cs + dc0 + c);
@@ -826,7 +839,7 @@ __global__ void k_up2_bwd8(const __bf16 *__restrict__ dout, int N, int h, int w,
     bf16x8 r;
 #pragma unroll
     for (int k = 0; k < 8; ++k) r[k] = (__bf16)((float)a0[k] + (float)a1[k] + (float)a2[k] + (float)a3[k]);
-    store8(din + q * C + c, r);
+    store8(din + ((int64_t)row * w + x) * C + c, r);
 }
 
 __global__ void k_slice8(const __bf16 *__restrict__ src, int s_cs, int sc0, __bf16 *__restrict__ dst, int d_cs, int dc0,
@@ -1035,6 +1048,24 @@ __global__ void k_cavity_fields(const __bf16 *__restrict__ out, int o_cs, const 
 }
 
 inline int blocks_for(int64_t n, int t = 256) { return (int)((n + t - 1) / t); }
+
+// Row grid of `width` pixels x C channels per row (C a multiple of 8), 256-thread blocks.
+inline RowGrid row_grid(int width, int C)
+{
+    RowGrid g;
+    g.C8 = C / 8;
+    g.items = width * g.C8;
+    g.bpr = (g.items + 255) / 256;
+    g.c8s = (g.C8 & (g.C8 - 1)) == 0 ? __builtin_ctz((unsigned)g.C8) : -1;
+    return g;
+}
+
+// The row grid's block count and per-row indices fit in 32 bits.
+inline bool row_grid_fits(int64_t rows, int64_t width, int64_t C)
+{
+    const int64_t items = width * (C / 8), bpr = (items + 255) / 256;
+    return rows * bpr < ((int64_t)1 << 31) && bpr * 256 < ((int64_t)1 << 31);
+}
 
 // Fixed-order sum of nchunk partial vectors of n floats, stride apart (n, stride and na
 // multiples of 4, 16-byte aligned); the first na sums go to out, the rest to out_b.
@@ -1294,9 +1325,12 @@ int ddf_nn_pool2(const void *in, int32_t N, int32_t H, int32_t W, int32_t C, int
     if (!in || !out || N <= 0 || H <= 0 || W <= 0 || C <= 0) return fail(DDF_ERR_ARG, "pool2: bad tensor arguments");
     if (H % 2 || W % 2) return fail(DDF_ERR_ARG, "pool2: H and W must be even");
     if (in_co < 0 || in_cs < in_co + C) return fail(DDF_ERR_ARG, "pool2: the channel stride must cover the channels");
-    if (C % 8 == 0 && in_cs % 8 == 0 && in_co % 8 == 0 && al16(in) && al16(out))
-        hipLaunchKernelGGL(k_pool2_8, dim3(blocks_for((int64_t)N * H * W * C / 32)), dim3(256), 0, (hipStream_t)stream,
-                           (const __bf16 *)in, N, H, W, C, in_cs, in_co, (__bf16 *)out);
+    if (C % 8 == 0 && in_cs % 8 == 0 && in_co % 8 == 0 && al16(in) && al16(out) &&
+        row_grid_fits((int64_t)N * (H / 2), W / 2, C)) {
+        const RowGrid g = row_grid(W / 2, C);
+        hipLaunchKernelGGL(k_pool2_8, dim3((unsigned)(N * (H / 2) * g.bpr)), dim3(256), 0, (hipStream_t)stream,
+                           (const __bf16 *)in, g, H, W, C, in_cs, in_co, (__bf16 *)out);
+    }
     else
         hipLaunchKernelGGL(k_pool2, dim3(blocks_for((int64_t)N * H * W * C / 4)), dim3(256), 0, (hipStream_t)stream,
                            (const __bf16 *)in, N, H, W, C, in_cs, in_co, (__bf16 *)out);
@@ -1310,10 +1344,12 @@ int ddf_nn_pool2_bwd(const void *dout, int32_t N, int32_t H, int32_t W, int32_t 
     if (H % 2 || W % 2) return fail(DDF_ERR_ARG, "pool2_bwd: H and W must be even");
     if (din_co < 0 || din_cs < din_co + C) return fail(DDF_ERR_ARG, "pool2_bwd: the channel stride must cover the channels");
     const __bf16 *mk = (const __bf16 *)mask;
-    if (C % 8 == 0 && din_cs % 8 == 0 && din_co % 8 == 0 && al16(dout) && al16(din) && (!mask || al16(mask)))
-        hipLaunchKernelGGL(k_pool2_bwd8, dim3(blocks_for((int64_t)N * H * W * C / 8)), dim3(256), 0,
-                           (hipStream_t)stream, (const __bf16 *)dout, N, H, W, C, (__bf16 *)din, din_cs, din_co, mk,
-                           accumulate);
+    if (C % 8 == 0 && din_cs % 8 == 0 && din_co % 8 == 0 && al16(dout) && al16(din) && (!mask || al16(mask)) &&
+        row_grid_fits((int64_t)N * H, W, C)) {
+        const RowGrid g = row_grid(W, C);
+        hipLaunchKernelGGL(k_pool2_bwd8, dim3((unsigned)(N * H * g.bpr)), dim3(256), 0, (hipStream_t)stream,
+                           (const __bf16 *)dout, g, H, W, C, (__bf16 *)din, din_cs, din_co, mk, accumulate);
+    }
     else
         hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks_for((int64_t)N * H * W * C)), dim3(256), 0, (hipStream_t)stream,
                            (const __bf16 *)dout, N, H, W, C, (__bf16 *)din, din_cs, din_co, mk, accumulate);
@@ -1323,9 +1359,12 @@ int ddf_nn_pool2_bwd(const void *dout, int32_t N, int32_t H, int32_t W, int32_t 
 int ddf_nn_up2(const void *in, int32_t N, int32_t h, int32_t w, int32_t C, void *out, int32_t out_cs, int32_t out_co,
                void *stream)
 {
-    if (C % 8 == 0 && out_cs % 8 == 0 && out_co % 8 == 0 && al16(in) && al16(out))
-        hipLaunchKernelGGL(k_up2_8, dim3(blocks_for((int64_t)N * 4 * h * w * C / 8)), dim3(256), 0, (hipStream_t)stream,
-                           (const __bf16 *)in, N, h, w, C, (__bf16 *)out, out_cs, out_co);
+    if (C % 8 == 0 && out_cs % 8 == 0 && out_co % 8 == 0 && al16(in) && al16(out) &&
+        row_grid_fits((int64_t)N * 2 * h, 2 * (int64_t)w, C)) {
+        const RowGrid g = row_grid(2 * w, C);
+        hipLaunchKernelGGL(k_up2_8, dim3((unsigned)(N * 2 * h * g.bpr)), dim3(256), 0, (hipStream_t)stream,
+                           (const __bf16 *)in, g, h, w, C, (__bf16 *)out, out_cs, out_co);
+    }
     else
         hipLaunchKernelGGL(k_up2, dim3(blocks_for((int64_t)N * 4 * h * w * C)), dim3(256), 0, (hipStream_t)stream,
                            (const __bf16 *)in, N, h, w, C, (__bf16 *)out, out_cs, out_co);
@@ -1335,9 +1374,11 @@ int ddf_nn_up2(const void *in, int32_t N, int32_t h, int32_t w, int32_t C, void 
 int ddf_nn_up2_bwd(const void *dout, int32_t N, int32_t h, int32_t w, int32_t C, int32_t d_cs, int32_t d_co, void *din,
                    void *stream)
 {
-    if (C % 8 == 0 && d_cs % 8 == 0 && d_co % 8 == 0 && al16(dout) && al16(din))
-        hipLaunchKernelGGL(k_up2_bwd8, dim3(blocks_for((int64_t)N * h * w * C / 8)), dim3(256), 0, (hipStream_t)stream,
-                           (const __bf16 *)dout, N, h, w, C, d_cs, d_co, (__bf16 *)din);
+    if (C % 8 == 0 && d_cs % 8 == 0 && d_co % 8 == 0 && al16(dout) && al16(din) && row_grid_fits((int64_t)N * h, w, C)) {
+        const RowGrid g = row_grid(w, C);
+        hipLaunchKernelGGL(k_up2_bwd8, dim3((unsigned)(N * h * g.bpr)), dim3(256), 0, (hipStream_t)stream,
+                           (const __bf16 *)dout, g, h, w, C, d_cs, d_co, (__bf16 *)din);
+    }
     else
         hipLaunchKernelGGL(k_up2_bwd, dim3(blocks_for((int64_t)N * h * w * C)), dim3(256), 0, (hipStream_t)stream,
                            (const __bf16 *)dout, N, h, w, C, d_cs, d_co, (__bf16 *)din);

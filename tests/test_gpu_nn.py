@@ -257,6 +257,41 @@ def test_pool_reads_and_adjoint_writes_channel_slices(C, cs, co, accumulate):
     assert np.array_equal(got[..., keep], g0[..., keep])
 
 
+@pytest.mark.parametrize("B,H,W,C,cs,co", [
+    (2, 6, 40, 24, 40, 8),      # C / 8 = 3: lanes find their pixel by division
+    (3, 4, 72, 64, 96, 32),     # 576 lanes per full-resolution row: three blocks, the last one ragged
+    (1, 2, 520, 8, 8, 0),       # one channel group, 520 pixels per row
+])
+def test_resampling_kernels_on_multi_block_rows(B, H, W, C, cs, co):
+    # the 16-byte pooling and upsampling kernels and their adjoints run on a grid of
+    # pixel rows (several blocks per row): slices of a wider tensor, against the oracle
+    r = np.random.default_rng(B * 1000 + W)
+    xt, x = bf(r.standard_normal((B, H, W, cs)))
+    pooled = torch.empty(B * H * W * C // 4, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_pool2(p(xt), B, H, W, C, cs, co, p(pooled), s0()))
+    xs = x[..., co:co + C]
+    assert_bf16_ulp(np_of(pooled, (B, H // 2, W // 2, C)), U.pool2(xs), U.pool2(np.abs(xs)), 4)
+    pq = np_of(pooled, (B, H // 2, W // 2, C))
+    mt, mq = bf(r.standard_normal((B, H, W, cs)))
+    gt, g0 = bf(r.standard_normal((B, H, W, cs)))
+    L.check(L.lib().ddf_nn_pool2_bwd(p(pooled), B, H, W, C, p(gt), cs, co, p(mt), 1, s0()))
+    got = np_of(gt, (B, H, W, cs))
+    want = np.where(mq[..., co:co + C] > 0, U.pool2_backward(pq), 0.0)
+    assert_bf16_ulp(got[..., co:co + C], want + g0[..., co:co + C], np.abs(want) + np.abs(g0[..., co:co + C]), 1)
+    keep = np.ones(cs, bool)
+    keep[co:co + C] = False
+    assert np.array_equal(got[..., keep], g0[..., keep])
+    up = torch.zeros(B * H * W * cs, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_up2(p(pooled), B, H // 2, W // 2, C, p(up), cs, co, s0()))
+    ug = np_of(up, (B, H, W, cs))
+    assert np.array_equal(ug[..., co:co + C], U.up2(pq)) and not np.any(ug[..., keep])
+    ht, hq = bf(r.standard_normal((B, H, W, cs)))
+    din = torch.empty(B * H * W * C // 4, dtype=torch.bfloat16, device=DEV)
+    L.check(L.lib().ddf_nn_up2_bwd(p(ht), B, H // 2, W // 2, C, cs, co, p(din), s0()))
+    hs = hq[..., co:co + C]
+    assert_bf16_ulp(np_of(din, pq.shape), U.up2_backward(hs), U.up2_backward(np.abs(hs)), 4)
+
+
 def test_pool_rejects_strides_that_miss_the_channels():
     x = torch.zeros(2 * 4 * 4 * 16, dtype=torch.bfloat16, device=DEV)
     o = torch.zeros(2 * 2 * 2 * 16, dtype=torch.bfloat16, device=DEV)
