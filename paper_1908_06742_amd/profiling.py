@@ -35,7 +35,25 @@ def counter_means(db, counter):
     return {r[0]: (r[1], r[2]) for r in rows}
 
 
+def readable(name):
+    """A mangled nested name the profiler left as is (_ZN<len><id>...E<params>) as
+    scope::name(...); anything else unchanged."""
+    if not name.startswith("_ZN"):
+        return name
+    parts, i = [], 3
+    while i < len(name) and name[i].isdigit():
+        j = i
+        while j < len(name) and name[j].isdigit():
+            j += 1
+        k = int(name[i:j])
+        ident = name[j:j + k]
+        parts.append("(anonymous namespace)" if ident.startswith("_GLOBAL__N") else ident)
+        i = j + k
+    return "::".join(parts) + "(...)" if parts else name
+
+
 def short(name, n=90):
+    name = readable(name)
     return name if len(name) <= n else name[: n - 3] + "..."
 
 

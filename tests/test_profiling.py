@@ -79,3 +79,10 @@ def test_counters_scale_by_the_copy_calibration(tmp_path, capsys):
     assert per["k_step<odd>"]["fetch_bytes"] == 2200.0 * 1024
     assert d["bytes_per_launch"] == ((2000.0 + 2000.0) + (2200.0 + 2000.0)) * 1024 / 2
     assert d["algorithmic_bytes_per_launch"] == 4000 and "kernel_hash" in d
+
+
+def test_mangled_names_left_by_the_profiler_are_shortened():
+    assert P.readable("_ZN12_GLOBAL__N_110k_up2_bwd8EPKDF16bNS_7RowGridEiiiiiPDF16b") == \
+        "(anonymous namespace)::k_up2_bwd8(...)"
+    assert P.readable("_ZN3ddf6k_stepIfLi0EEEvPT_") == "ddf::k_step(...)"
+    assert P.readable("void ddf::k_step<float>(float*)") == "void ddf::k_step<float>(float*)"
