@@ -75,6 +75,28 @@ def time_parities(lat, stream, pairs=20):
     return {p: sum(a.elapsed_time(b) for a, b in v) / len(v) for p, v in ev.items()}
 
 
+def time_pattern(lat, stream, caps=(1, 2, 3), launches=8):
+    """The step's access pattern without its collision (ddf_pattern_probe) on the
+    lattice's own populations: mean ms per launch of each parity at each cap on resident
+    workgroups per CU (an even number of launches per parity restores the populations)."""
+    import torch
+
+    out = {}
+    for cap in caps:
+        row = {}
+        for par in (0, 1):
+            lat.pattern_probe(par, cap)     # warm-up (and the pair to the odd count below)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(launches - 1):
+                lat.pattern_probe(par, cap)
+            e1.record(stream)
+            e1.synchronize()
+            row[par] = e0.elapsed_time(e1) / (launches - 1)
+        out[cap] = row
+    return out
+
+
 def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=None, scalar_model="mrt",
             pulsatile=False, time_extract=False, parity_steps=False):
     import numpy as np
@@ -127,6 +149,7 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=No
     kern_ms = sum(a.elapsed_time(b) for a, b in evs) / (steps * lb_steps)
     stats = dict(last)
     parity_ms = time_parities(lat, stream) if parity_steps else None
+    pattern_ms = time_pattern(lat, stream) if parity_steps else None
     extract_ms = None
     if time_extract:
         # all 16 outputs (rho, u, phi, S, omega, gradients, Q, R, Lamb vector) in FP32
@@ -149,6 +172,7 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=No
         "launch": launch,
         "extract_ms": extract_ms,
         "parity_ms": parity_ms,
+        "pattern_ms": pattern_ms,
     }
 
 
@@ -531,6 +555,9 @@ def main():
     traffic = measured_traffic(nodes, r["tile_width"]) if args.storage == "f32" and args.size == 8192 else None
     ceil = stream_ceilings()
     cgbs = ceil["copy_gbs"]
+    pat = {cap: {"even_ms": round(v[0], 4), "odd_ms": round(v[1], 4),
+                 "gbs": round(bpn * nodes / (0.5 * (v[0] + v[1]) * 1e-3) / 1e9, 1)} for cap, v in r["pattern_ms"].items()}
+    pcap = max(pat, key=lambda c: pat[c]["gbs"])
     line = {
         "metric": "MLUPS (fluid+scalar D2Q9 node-updates per second / 1e6)",
         "value": round(r["mlups"], 1),
@@ -570,6 +597,12 @@ def main():
             "copy_gbs": cgbs,
             "frac_of_copy": round(achieved / cgbs, 4),
             "stream_ceilings": ceil,
+            # the same loads and stores without the collision (ddf_pattern_probe), best
+            # cap on resident workgroups per CU
+            "pattern_gbs": pat[pcap]["gbs"],
+            "pattern_wg_per_cu": pcap,
+            "frac_of_pattern": round(achieved / pat[pcap]["gbs"], 4),
+            "pattern_by_wg_per_cu": pat,
         },
         "final_stats": {k: r["stats"][k] for k in ("mass", "scalar", "res_u", "nonfinite")},
     }

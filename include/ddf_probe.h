@@ -6,7 +6,8 @@
  * (it reads and writes every population once per time step and does 1-2 flops per
  * byte), so its achieved GB/s is compared with the nominal HBM peak and with what a
  * plain stream reaches on the same device: a copy (each byte read once and written
- * once, like the step), a read-only and a write-only pass.
+ * once, like the step), a read-only and a write-only pass; and with the step's own
+ * access pattern run without its arithmetic.
  *
  * Conventions: as in ddf.h (caller-owned device buffers, asynchronous on `stream`,
  * DDF_OK or a negative ddf_status, message in ddf_last_error()).
@@ -16,6 +17,8 @@
 
 #include <stddef.h>
 #include <stdint.h>
+
+#include "ddf.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -32,6 +35,20 @@ enum { DDF_PROBE_COPY = 0, DDF_PROBE_READ = 1, DDF_PROBE_WRITE = 2 };
  * must not overlap.  DDF_ERR_ARG for anything else. */
 int ddf_bandwidth_probe(int32_t kind, int32_t unroll, int32_t nontemporal, const void *src, void *dst, size_t bytes,
                         void *stream);
+
+/* The memory accesses of one AA step of the given parity (0 even, 1 odd) over the
+ * populations of handle h, without the collision: per node, the nine stored
+ * populations of each lattice that the step of that parity loads are loaded, and each
+ * is stored where the step stores the population of the opposite direction (in the
+ * in-place AA pattern that is the slot the step loaded as that direction).  Same
+ * tiles, tile-to-XCD map, row layout, lane offsets and non-temporal policy as the
+ * handle's step kernels; wg_per_cu caps the resident workgroups per CU (0 = no cap, 1-3),
+ * like ddf_set_workgroups_per_cu.  It swaps opposite directions within each node's slot
+ * set, so two calls of one parity leave the populations bit-identical; the step count
+ * is not changed.  Periodic lattices only (DDF_ERR_UNSUPPORTED with walls).  Runs on
+ * `stream`, which must be ordered after the handle's earlier work.  DDF_ERR_ARG for a
+ * NULL handle, another parity or cap. */
+int ddf_pattern_probe(ddf_handle *h, int32_t parity, int32_t wg_per_cu, void *stream);
 
 #ifdef __cplusplus
 }

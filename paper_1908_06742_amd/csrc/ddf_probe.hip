@@ -1,6 +1,6 @@
 // libddf HBM reference kernels (include/ddf_probe.h): a copy, a read-only and a
-// write-only pass over a buffer, the ceilings the bandwidth-bound step kernels are
-// measured against.
+// write-only pass over a buffer, and the step's own access pattern without its
+// arithmetic: the ceilings the bandwidth-bound step kernels are measured against.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -8,7 +8,7 @@
 
 #include "../../include/ddf.h"
 #include "../../include/ddf_probe.h"
-#include "ddf_kernels.hpp"
+#include "ddf_handle.hpp"
 
 namespace {
 
@@ -92,6 +92,52 @@ void launch_kind(int unroll, bool nt, const void *src, void *dst, int64_t n4, hi
     }
 }
 
+// The step's memory accesses with the collision left out: every thread loads the nine
+// stored populations of both lattices that the step of this parity loads for its node
+// and stores each where the step stores the population of the opposite direction,
+// which is the slot the step loaded as that direction (the same tiles, tile-to-XCD
+// map, lane offsets and non-temporal policy as the periodic step kernels).  Within a
+// node's slot set this swaps the pairs of opposite directions, so two launches of one
+// parity restore the populations bit for bit.
+template <class S, bool ODD, bool IDX32, int LY>
+__global__ __launch_bounds__(ddf::kThreads) void k_pattern(S *__restrict__ f, S *__restrict__ g, const ddf::Geom G)
+{
+    using namespace ddf;
+    constexpr bool NT = LY == LY_IL;
+    const int tile = tile_of_block();
+    if (tile >= G.ntiles) return;
+    int m, y;
+    if (!tile_node(tile, G.bx_shift, G.by, G.tiles_x, G.L.nx, G.L.ny, m, y)) return;
+    const int x = x_of<LY>(G.L, m);
+    int pa[9];
+    int64_t c[9];
+    S vf[9], vg[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        c[a] = logical_cell<false, ODD, LY>(G.L, x, y, a, pa[a]);
+        vf[a] = ld_pop<NT>(&elem<IDX32>(f, G.L, pa[a], c[a]));
+    }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) vg[a] = ld_pop<NT>(&elem<IDX32>(g, G.L, pa[a], c[a]));
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        st_pop<NT>(&elem<IDX32>(f, G.L, pa[opp(a)], c[opp(a)]), vf[a]);
+        st_pop<NT>(&elem<IDX32>(g, G.L, pa[opp(a)], c[opp(a)]), vg[a]);
+    }
+}
+
+template <class S, bool ODD, bool IDX32>
+void launch_pattern(const ddf_handle *h, int lds, hipStream_t st)
+{
+    using namespace ddf;
+    if (h->G.L.qs)
+        hipLaunchKernelGGL((k_pattern<S, ODD, IDX32, LY_IL>), dim3(h->nblocks), dim3(kThreads), lds, st, (S *)h->f,
+                           (S *)h->g, h->G);
+    else
+        hipLaunchKernelGGL((k_pattern<S, ODD, IDX32, LY_ROW>), dim3(h->nblocks), dim3(kThreads), lds, st, (S *)h->f,
+                           (S *)h->g, h->G);
+}
+
 }  // namespace
 
 extern "C" int ddf_bandwidth_probe(int32_t kind, int32_t unroll, int32_t nontemporal, const void *src, void *dst,
@@ -119,5 +165,32 @@ extern "C" int ddf_bandwidth_probe(int32_t kind, int32_t unroll, int32_t nontemp
     else launch_kind<DDF_PROBE_WRITE>(unroll, nt, src, dst, n4, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DDF_ERR_HIP, std::string("probe launch: ") + hipGetErrorString(e));
+    return DDF_OK;
+}
+
+extern "C" int ddf_pattern_probe(ddf_handle *h, int32_t parity, int32_t wg_per_cu, void *stream)
+{
+    using ddf::host::fail;
+    if (!h) return fail(DDF_ERR_ARG, "pattern probe: handle is NULL");
+    if (ddf::host::has_walls(h->p))
+        return fail(DDF_ERR_UNSUPPORTED, "pattern probe: periodic lattices only (walls change the step's stores)");
+    if (parity != 0 && parity != 1) return fail(DDF_ERR_ARG, "pattern probe: parity must be 0 (even) or 1 (odd)");
+    if (wg_per_cu < 0 || wg_per_cu > 3)
+        return fail(DDF_ERR_ARG, "pattern probe: workgroups per CU must be 0 (no limit), 1, 2 or 3");
+    const int lds = ddf::host::cap_lds_bytes(wg_per_cu);
+    hipStream_t st = (hipStream_t)stream;
+    ddf::host::with_storage(h->p.storage, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        if (parity) {
+            if (h->idx32) launch_pattern<S, true, true>(h, lds, st);
+            else launch_pattern<S, true, false>(h, lds, st);
+        } else {
+            if (h->idx32) launch_pattern<S, false, true>(h, lds, st);
+            else launch_pattern<S, false, false>(h, lds, st);
+        }
+        return 0;
+    });
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DDF_ERR_HIP, std::string("pattern probe launch: ") + hipGetErrorString(e));
     return DDF_OK;
 }

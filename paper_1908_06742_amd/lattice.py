@@ -174,6 +174,13 @@ class Lattice:
         L.check(L.lib().ddf_get_workgroups_per_cu(self._h, C.byref(e), C.byref(o)))
         return int(e.value), int(o.value)
 
+    def pattern_probe(self, parity, wg_per_cu=0):
+        """The step's memory accesses of one parity without its collision (a reference
+        for the step's bandwidth; periodic lattices): swaps opposite directions in each
+        node's slot set, so two calls of one parity restore the populations."""
+        L.check(L.lib().ddf_pattern_probe(self._h, int(parity), int(wg_per_cu), _stream_ptr(self.stream)))
+        return self
+
     def set_graph(self, steps_per_graph):
         """Steps per captured hipGraph replay (even; 0 = eager launches)."""
         L.check(L.lib().ddf_set_graph(self._h, int(steps_per_graph)))

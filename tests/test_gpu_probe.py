@@ -1,11 +1,14 @@
 """The HBM reference kernels (include/ddf_probe.h) move exactly the bytes they claim:
 the copy reproduces its source bit for bit, the write pass zeroes its destination and
-the read pass leaves every buffer untouched."""
+the read pass leaves every buffer untouched; the step's access pattern without its
+collision moves every population where the step of that parity moves it."""
 import ctypes as C
 
 import pytest
 import torch
 
+import workloads as W
+from paper_1908_06742_amd import Lattice
 from paper_1908_06742_amd import _lib as L
 
 pytestmark = pytest.mark.gpu
@@ -37,3 +40,49 @@ def test_probe_passes_move_exactly_their_bytes(unroll, nt):
     _probe(L.PROBE_WRITE, unroll, nt, None, dst, 4 * n)
     torch.cuda.synchronize()
     assert torch.all(dst[:n] == 0) and torch.all(dst[n:] == -7)
+
+
+OPP = [0, 3, 4, 1, 2, 7, 8, 5, 6]
+EX = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+EY = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+RAW = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
+
+
+@pytest.mark.parametrize("storage,nx,ny,layout,cap", [
+    ("f32", 2048, 24, "interleaved", 2),   # x-interleaved rows: the sub-row wrap of the x-shifts
+    ("f32", 96, 40, "row", 0),             # padded rows, a ragged last tile
+    ("f64", 1024, 8, "interleaved", 1),
+    ("f16", 4096, 6, "interleaved", 3),
+    ("bf16", 200, 30, "packed", 0),
+])
+def test_pattern_probe_moves_populations_like_the_step_without_collision(storage, nx, ny, layout, cap):
+    print(f"case: pattern probe {storage} {nx}x{ny} {layout} cap {cap}", flush=True)
+    lat = Lattice(W.Problem(nx=nx, ny=ny, storage=storage, layout=layout), device=DEV)
+    g = torch.Generator().manual_seed(nx + ny)
+    f0 = torch.randn((9, ny, nx), generator=g).to(RAW[storage])
+    g0 = torch.randn((9, ny, nx), generator=g).to(RAW[storage])
+    lat.set_populations(f0, g0, step=0, raw=True)
+
+    def pops():
+        f, gg = lat.get_populations(raw=True)
+        torch.cuda.synchronize()
+        return f.cpu(), gg.cpu()
+
+    # even: the node's own slots, each population into the opposite direction's slot
+    lat.pattern_probe(0, cap)
+    f1, g1 = pops()
+    assert torch.equal(f1, f0[OPP]) and torch.equal(g1, g0[OPP])
+    lat.pattern_probe(0, cap)
+    f1, g1 = pops()
+    assert torch.equal(f1, f0) and torch.equal(g1, g0)
+    # odd: from slot opp(a) of x - c_a to slot a of x + c_a; read back as an even-step
+    # state, direction a at z holds direction opp(a) of z - 2 c_a
+    lat.pattern_probe(1, cap)
+    f2, g2 = pops()
+    for a in range(9):
+        sh = (2 * EY[a], 2 * EX[a])
+        assert torch.equal(f2[a], torch.roll(f0[OPP[a]], sh, dims=(0, 1))), a
+        assert torch.equal(g2[a], torch.roll(g0[OPP[a]], sh, dims=(0, 1))), a
+    lat.pattern_probe(1, cap)
+    f2, g2 = pops()
+    assert torch.equal(f2, f0) and torch.equal(g2, g0) and lat.step_count == 0
