@@ -39,12 +39,13 @@ int ddf_bandwidth_probe(int32_t kind, int32_t unroll, int32_t nontemporal, const
 /* The memory accesses of one AA step of the given parity (0 even, 1 odd) over the
  * populations of handle h, without the collision: per node, the nine stored
  * populations of each lattice that the step of that parity loads are loaded, and each
- * is stored where the step stores the population of the opposite direction (in the
- * in-place AA pattern that is the slot the step loaded as that direction).  Same
+ * is stored, sign bit flipped, where the step stores the population of the opposite
+ * direction (in the in-place AA pattern that is the slot the step loaded as that
+ * direction; the flip keeps the rest direction's copy onto itself a real store).  Same
  * tiles, tile-to-XCD map, row layout, lane offsets and non-temporal policy as the
  * handle's step kernels; wg_per_cu caps the resident workgroups per CU (0 = no cap, 1-3),
- * like ddf_set_workgroups_per_cu.  It swaps opposite directions within each node's slot
- * set, so two calls of one parity leave the populations bit-identical; the step count
+ * like ddf_set_workgroups_per_cu.  It swaps and negates opposite directions within each
+ * node's slot set, so two calls of one parity leave the populations bit-identical; the step count
  * is not changed.  Periodic lattices only (DDF_ERR_UNSUPPORTED with walls).  Runs on
  * `stream`, which must be ordered after the handle's earlier work.  DDF_ERR_ARG for a
  * NULL handle, another parity or cap. */

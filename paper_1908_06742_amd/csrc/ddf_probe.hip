@@ -92,13 +92,25 @@ void launch_kind(int unroll, bool nt, const void *src, void *dst, int64_t n4, hi
     }
 }
 
+// A stored population with its sign bit flipped (every storage format keeps the sign in
+// its top bit): the probe stores values that differ from what it loaded, so no load or
+// store can be dropped as a copy of a slot onto itself (the rest direction's would be).
+__device__ __forceinline__ float flip_sign(float v) { return __uint_as_float(__float_as_uint(v) ^ 0x80000000u); }
+__device__ __forceinline__ double flip_sign(double v)
+{
+    return __longlong_as_double(__double_as_longlong(v) ^ (long long)0x8000000000000000ull);
+}
+__device__ __forceinline__ _Float16 flip_sign(_Float16 v) { return -v; }
+__device__ __forceinline__ ddf::bf16 flip_sign(ddf::bf16 v) { return ddf::bf16{(uint16_t)(v.bits ^ 0x8000u)}; }
+__device__ __forceinline__ ddf::bf16sr flip_sign(ddf::bf16sr v) { return ddf::bf16sr{(uint16_t)(v.bits ^ 0x8000u)}; }
+
 // The step's memory accesses with the collision left out: every thread loads the nine
 // stored populations of both lattices that the step of this parity loads for its node
-// and stores each where the step stores the population of the opposite direction,
-// which is the slot the step loaded as that direction (the same tiles, tile-to-XCD
-// map, lane offsets and non-temporal policy as the periodic step kernels).  Within a
-// node's slot set this swaps the pairs of opposite directions, so two launches of one
-// parity restore the populations bit for bit.
+// and stores each, sign flipped, where the step stores the population of the opposite
+// direction, which is the slot the step loaded as that direction (the same tiles,
+// tile-to-XCD map, lane offsets and non-temporal policy as the periodic step kernels).
+// Within a node's slot set this swaps the pairs of opposite directions and negates
+// them, so two launches of one parity restore the populations bit for bit.
 template <class S, bool ODD, bool IDX32, int LY>
 __global__ __launch_bounds__(ddf::kThreads) void k_pattern(S *__restrict__ f, S *__restrict__ g, const ddf::Geom G)
 {
@@ -121,8 +133,8 @@ __global__ __launch_bounds__(ddf::kThreads) void k_pattern(S *__restrict__ f, S 
     for (int a = 0; a < 9; ++a) vg[a] = ld_pop<NT>(&elem<IDX32>(g, G.L, pa[a], c[a]));
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        st_pop<NT>(&elem<IDX32>(f, G.L, pa[opp(a)], c[opp(a)]), vf[a]);
-        st_pop<NT>(&elem<IDX32>(g, G.L, pa[opp(a)], c[opp(a)]), vg[a]);
+        st_pop<NT>(&elem<IDX32>(f, G.L, pa[opp(a)], c[opp(a)]), flip_sign(vf[a]));
+        st_pop<NT>(&elem<IDX32>(g, G.L, pa[opp(a)], c[opp(a)]), flip_sign(vg[a]));
     }
 }
 
