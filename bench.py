@@ -98,7 +98,7 @@ def time_pattern(lat, stream, caps=(1, 2, 3), launches=8):
 
 
 def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=None, scalar_model="mrt",
-            pulsatile=False, time_extract=False, parity_steps=False):
+            pulsatile=False, time_extract=False, parity_steps=False, pattern=None):
     import numpy as np
     import torch
 
@@ -149,7 +149,7 @@ def run_gpu(L, storage, steps, warmup, lb_steps=LB_STEPS_PER_STEP, tile_width=No
     kern_ms = sum(a.elapsed_time(b) for a, b in evs) / (steps * lb_steps)
     stats = dict(last)
     parity_ms = time_parities(lat, stream) if parity_steps else None
-    pattern_ms = time_pattern(lat, stream) if parity_steps else None
+    pattern_ms = time_pattern(lat, stream) if (parity_steps if pattern is None else pattern) else None
     extract_ms = None
     if time_extract:
         # all 16 outputs (rho, u, phi, S, omega, gradients, Q, R, Lamb vector) in FP32
@@ -624,11 +624,18 @@ def main():
         for c in cases:
             st = c["storage"]
             print(f"[bench] variant 8192^2 {c}", file=sys.stderr, flush=True)
+            plain = len(c) == 1      # a storage format alone: also its access pattern without the collision
             v = run_gpu(8192, st, 3, 1, scalar_model=c.get("scalar_model", "mrt"), pulsatile=c.get("pulsatile", False),
-                        time_extract=c.get("time_extract", False))
+                        time_extract=c.get("time_extract", False), pattern=plain)
             ach = BYTES_PER_NODE[st] * v["nodes"] / (v["kernel_ms"] * 1e-3) / 1e9
             row = {**c, "size": 8192, "mlups": round(v["mlups"], 1), "kernel_gbs": round(ach, 1),
                    "frac": round(ach / HBM_PEAK_GBS, 4), "tile_width": v["tile_width"], "launch": v["launch"]}
+            if v["pattern_ms"]:
+                pg = {cap: BYTES_PER_NODE[st] * v["nodes"] / (0.5 * (e + o) * 1e-3) / 1e9
+                      for cap, (e, o) in ((k, (t[0], t[1])) for k, t in v["pattern_ms"].items())}
+                best = max(pg, key=pg.get)
+                row.update({"pattern_gbs": round(pg[best], 1), "pattern_wg_per_cu": best,
+                            "frac_of_pattern": round(ach / pg[best], 4)})
             if v["extract_ms"] is not None:
                 # reads both lattices once (half the step's bytes: 72 B/node in FP32) and
                 # writes 16 FP32 outputs (64 B/node)
