@@ -226,6 +226,15 @@ def run_cavity(n=1024, cap=200_000, tol=1e-8):
     ecc = err(c, wz - pred) if bool(c.any()) else None
     # the term alone, against the whole difference
     share = float(torch.linalg.norm(pred[m]) / torch.linalg.norm((wz - curl)[m]))
+    # the step kernels alone (per parity), and the same accesses without the collision;
+    # bytes per second of a cache-resident lattice, not an HBM figure
+    stream = torch.cuda.current_stream()
+    par = time_parities(lat, stream)
+    pat = time_pattern(lat, stream)
+    nb = BYTES_PER_NODE["f32"] * n * n
+    pg = {cap: nb / (0.5 * (v[0] + v[1]) * 1e-3) / 1e9 for cap, v in pat.items()}
+    pcap = max(pg, key=pg.get)
+    kg = nb / (0.5 * (par[0] + par[1]) * 1e-3) / 1e9
     return {"workload": f"lid-driven cavity {n}^2, Re 1000, U 0.1, f32, to r < {tol:g} or {cap} steps",
             "mlups": round(n * n * r["steps"] / dt / 1e6, 1), "steps": r["steps"], "status": r["status"],
             "seconds": round(dt, 3), "res_u": r["res_u"], "res_phi": r["res_phi"],
@@ -233,7 +242,9 @@ def run_cavity(n=1024, cap=200_000, tol=1e-8):
             "omega_vs_fd_curl_rel_l2": ew, "omega_vs_fd_curl_rel_l2_centre_quarter": ec,
             "omega_minus_curvature_term_vs_fd_curl_rel_l2": ewc,
             "omega_minus_curvature_term_vs_fd_curl_rel_l2_centre_quarter": ecc,
-            "curvature_term_over_difference_l2": share}
+            "curvature_term_over_difference_l2": share,
+            "kernel_ms_even": round(par[0], 4), "kernel_ms_odd": round(par[1], 4), "kernel_gbs": round(kg, 1),
+            "pattern_gbs": round(pg[pcap], 1), "pattern_wg_per_cu": pcap, "frac_of_pattern": round(kg / pg[pcap], 4)}
 
 
 def stream_ceilings(nbytes=2 << 30, reps=5):

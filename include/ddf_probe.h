@@ -46,9 +46,9 @@ int ddf_bandwidth_probe(int32_t kind, int32_t unroll, int32_t nontemporal, const
  * handle's step kernels; wg_per_cu caps the resident workgroups per CU (0 = no cap, 1-3),
  * like ddf_set_workgroups_per_cu.  It swaps and negates opposite directions within each
  * node's slot set, so two calls of one parity leave the populations bit-identical; the step count
- * is not changed.  Periodic lattices only (DDF_ERR_UNSUPPORTED with walls).  Runs on
- * `stream`, which must be ordered after the handle's earlier work.  DDF_ERR_ARG for a
- * NULL handle, another parity or cap. */
+ * is not changed.  With walls, a link the step reflects is loaded from and stored to the
+ * node's own slots, as in the step.  Runs on `stream`, which must be ordered after the
+ * handle's earlier work.  DDF_ERR_ARG for a NULL handle, another parity or cap. */
 int ddf_pattern_probe(ddf_handle *h, int32_t parity, int32_t wg_per_cu, void *stream);
 
 #ifdef __cplusplus

@@ -110,8 +110,10 @@ __device__ __forceinline__ ddf::bf16sr flip_sign(ddf::bf16sr v) { return ddf::bf
 // direction, which is the slot the step loaded as that direction (the same tiles,
 // tile-to-XCD map, lane offsets and non-temporal policy as the periodic step kernels).
 // Within a node's slot set this swaps the pairs of opposite directions and negates
-// them, so two launches of one parity restore the populations bit for bit.
-template <class S, bool ODD, bool IDX32, int LY>
+// them, so two launches of one parity restore the populations bit for bit.  Walls keep
+// that form: a link that the step reflects is loaded from, and stored to, the node's
+// own slots, exactly as the step does.
+template <class S, bool WALLS, bool ODD, bool IDX32, int LY>
 __global__ __launch_bounds__(ddf::kThreads) void k_pattern(S *__restrict__ f, S *__restrict__ g, const ddf::Geom G)
 {
     using namespace ddf;
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(ddf::kThreads) void k_pattern(S *__restrict__ f, S 
     S vf[9], vg[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        c[a] = logical_cell<false, ODD, LY>(G.L, x, y, a, pa[a]);
+        c[a] = logical_cell<WALLS, ODD, LY>(G.L, x, y, a, pa[a]);
         vf[a] = ld_pop<NT>(&elem<IDX32>(f, G.L, pa[a], c[a]));
     }
 #pragma unroll
@@ -138,16 +140,28 @@ __global__ __launch_bounds__(ddf::kThreads) void k_pattern(S *__restrict__ f, S 
     }
 }
 
-template <class S, bool ODD, bool IDX32>
+template <class S, bool WALLS, bool ODD, bool IDX32>
 void launch_pattern(const ddf_handle *h, int lds, hipStream_t st)
 {
     using namespace ddf;
     if (h->G.L.qs)
-        hipLaunchKernelGGL((k_pattern<S, ODD, IDX32, LY_IL>), dim3(h->nblocks), dim3(kThreads), lds, st, (S *)h->f,
-                           (S *)h->g, h->G);
+        hipLaunchKernelGGL((k_pattern<S, WALLS, ODD, IDX32, LY_IL>), dim3(h->nblocks), dim3(kThreads), lds, st,
+                           (S *)h->f, (S *)h->g, h->G);
     else
-        hipLaunchKernelGGL((k_pattern<S, ODD, IDX32, LY_ROW>), dim3(h->nblocks), dim3(kThreads), lds, st, (S *)h->f,
-                           (S *)h->g, h->G);
+        hipLaunchKernelGGL((k_pattern<S, WALLS, ODD, IDX32, LY_ROW>), dim3(h->nblocks), dim3(kThreads), lds, st,
+                           (S *)h->f, (S *)h->g, h->G);
+}
+
+template <class S, bool WALLS>
+void launch_pattern_parity(const ddf_handle *h, bool odd, int lds, hipStream_t st)
+{
+    if (odd) {
+        if (h->idx32) launch_pattern<S, WALLS, true, true>(h, lds, st);
+        else launch_pattern<S, WALLS, true, false>(h, lds, st);
+    } else {
+        if (h->idx32) launch_pattern<S, WALLS, false, true>(h, lds, st);
+        else launch_pattern<S, WALLS, false, false>(h, lds, st);
+    }
 }
 
 }  // namespace
@@ -184,8 +198,6 @@ extern "C" int ddf_pattern_probe(ddf_handle *h, int32_t parity, int32_t wg_per_c
 {
     using ddf::host::fail;
     if (!h) return fail(DDF_ERR_ARG, "pattern probe: handle is NULL");
-    if (ddf::host::has_walls(h->p))
-        return fail(DDF_ERR_UNSUPPORTED, "pattern probe: periodic lattices only (walls change the step's stores)");
     if (parity != 0 && parity != 1) return fail(DDF_ERR_ARG, "pattern probe: parity must be 0 (even) or 1 (odd)");
     if (wg_per_cu < 0 || wg_per_cu > 3)
         return fail(DDF_ERR_ARG, "pattern probe: workgroups per CU must be 0 (no limit), 1, 2 or 3");
@@ -193,13 +205,8 @@ extern "C" int ddf_pattern_probe(ddf_handle *h, int32_t parity, int32_t wg_per_c
     hipStream_t st = (hipStream_t)stream;
     ddf::host::with_storage(h->p.storage, [&](auto *tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        if (parity) {
-            if (h->idx32) launch_pattern<S, true, true>(h, lds, st);
-            else launch_pattern<S, true, false>(h, lds, st);
-        } else {
-            if (h->idx32) launch_pattern<S, false, true>(h, lds, st);
-            else launch_pattern<S, false, false>(h, lds, st);
-        }
+        if (ddf::host::has_walls(h->p)) launch_pattern_parity<S, true>(h, parity != 0, lds, st);
+        else launch_pattern_parity<S, false>(h, parity != 0, lds, st);
         return 0;
     });
     hipError_t e = hipGetLastError();

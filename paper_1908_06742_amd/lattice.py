@@ -176,7 +176,7 @@ class Lattice:
 
     def pattern_probe(self, parity, wg_per_cu=0):
         """The step's memory accesses of one parity without its collision (a reference
-        for the step's bandwidth; periodic lattices): swaps opposite directions in each
+        for the step's bandwidth): swaps opposite directions in each
         node's slot set and flips their signs, so two calls of one parity restore the
         populations."""
         L.check(L.lib().ddf_pattern_probe(self._h, int(parity), int(wg_per_cu), _stream_ptr(self.stream)))

@@ -225,7 +225,7 @@ def test_pattern_probe_rejects_invalid_arguments_before_any_launch():
     assert "NULL" in lib.ddf_last_error().decode()
     for pr, cases in ((W.taylor_green_problem(16), ((2, 0, L.DDF_ERR_ARG, "parity"), (1, 4, L.DDF_ERR_ARG, "per CU"),
                                                     (0, -1, L.DDF_ERR_ARG, "per CU"))),
-                      (W.Problem(nx=16, ny=16, periodic_x=False, periodic_y=False), ((0, 0, L.DDF_ERR_UNSUPPORTED, "periodic"),))):
+                      (W.Problem(nx=16, ny=16, periodic_x=False, periodic_y=False), ((-1, 1, L.DDF_ERR_ARG, "parity"),))):
         p = L.params_from_problem(pr)
         h = C.c_void_p()
         assert lib.ddf_create(C.byref(p), C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20), C.byref(h)) == 0

@@ -4,6 +4,7 @@ the read pass leaves every buffer untouched; the step's access pattern without i
 collision moves every population where the step of that parity moves it."""
 import ctypes as C
 
+import numpy as np
 import pytest
 import torch
 
@@ -92,3 +93,68 @@ def test_pattern_probe_moves_populations_like_the_step_without_collision(storage
     lat.pattern_probe(1, cap)
     f2, g2 = pops()
     assert same(f2, f0) and same(g2, g0) and lat.step_count == 0
+
+
+def _odd_pattern_model(P, px, py):
+    """One odd pattern on memory P (9, ny, nx) in the natural slots of an even step: the
+    population of direction a loaded for node x (slot opp(a) of x - c_a, or slot a of x
+    itself when that link leaves through a wall) is stored negated where the step stores
+    direction opp(a)'s (slot a of x + c_a, or slot opp(a) of x at a wall)."""
+    ny, nx = P.shape[1:]
+    yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    out = np.empty_like(P)
+
+    def slot(a, sx, sy):
+        """slot of direction a read for nodes (xx, yy) from source nodes (sx, sy)"""
+        inside = np.ones_like(xx, bool)
+        if not px:
+            inside &= (sx >= 0) & (sx < nx)
+        if not py:
+            inside &= (sy >= 0) & (sy < ny)
+        plane = np.where(inside, OPP[a], a)
+        cy = np.where(inside, sy % ny, yy)
+        cx = np.where(inside, sx % nx, xx)
+        if a == 0:
+            plane, cy, cx = np.zeros_like(xx), yy, xx
+        return plane, cy, cx
+
+    for a in range(9):
+        lp, ly, lx = slot(a, xx - EX[a], yy - EY[a])
+        b = OPP[a]
+        sp, sy, sx = slot(b, xx - EX[b], yy - EY[b])
+        out[sp, sy, sx] = -P[lp, ly, lx]
+    return out
+
+
+@pytest.mark.parametrize("storage,nx,ny,layout,px,py", [
+    ("f32", 40, 24, "row", False, False),            # cavity: walls on all sides, corner links
+    ("f64", 64, 20, "row", True, False),             # channel: periodic in x
+    ("f32", 2048, 12, "interleaved", False, False),  # x-interleaved rows with walls
+])
+def test_pattern_probe_with_walls_reflects_where_the_step_does(storage, nx, ny, layout, px, py):
+    print(f"case: pattern probe walls {storage} {nx}x{ny} {layout} periodic {px},{py}", flush=True)
+    lat = Lattice(W.Problem(nx=nx, ny=ny, storage=storage, layout=layout, periodic_x=px, periodic_y=py), device=DEV)
+    g = torch.Generator().manual_seed(nx * ny)
+    f0 = torch.randn((9, ny, nx), generator=g).to(RAW[storage])
+    g0 = torch.randn((9, ny, nx), generator=g).to(RAW[storage])
+    lat.set_populations(f0, g0, step=0, raw=True)
+    bits = {4: torch.int32, 8: torch.int64}[f0.element_size()]
+
+    def same(a, b):
+        return torch.equal(a.contiguous().view(bits), torch.as_tensor(b).contiguous().view(bits))
+
+    def pops():
+        f, gg = lat.get_populations(raw=True)
+        torch.cuda.synchronize()
+        return f.cpu(), gg.cpu()
+
+    lat.pattern_probe(0, 0)
+    f1, g1 = pops()
+    assert same(f1, -f0[OPP]) and same(g1, -g0[OPP])
+    lat.pattern_probe(0, 0)
+    lat.pattern_probe(1, 0)
+    f2, g2 = pops()
+    assert same(f2, _odd_pattern_model(f0.numpy(), px, py)) and same(g2, _odd_pattern_model(g0.numpy(), px, py))
+    lat.pattern_probe(1, 0)
+    f2, g2 = pops()
+    assert same(f2, f0) and same(g2, g0)
