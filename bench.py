@@ -316,11 +316,38 @@ def run_batch(steps=20000, count=256):
     s = b.step_reduce(steps)
     dt = time.perf_counter() - t0
     nodes = b.total_nodes
+    # the step kernel per parity (eager launches) and the same accesses without the
+    # collision (ddf_batch_pattern_probe; 8 launches per parity restore the populations)
+    stream = torch.cuda.current_stream()
+    b.set_graph(0)
+    if b.step_count % 2:
+        b.step(1)
+
+    def mean_ms(fn, n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    pair = mean_ms(lambda: b.step(2), 10)
+    pat = [0.0, 0.0]
+    for par in (0, 1):
+        b.pattern_probe(par)
+        pat[par] = mean_ms(lambda: b.pattern_probe(par), 7)
+    b.set_graph(100)
+    kg = 144.0 * nodes / (0.5 * pair * 1e-3) / 1e9
+    pg = 144.0 * nodes / (0.5 * (pat[0] + pat[1]) * 1e-3) / 1e9
     return {"instances": count, "nodes": nodes, "mlups": round(nodes * steps / dt / 1e6, 1), "steps": steps,
             "seconds": round(dt, 3), "tiling": b.tiling(), "nontemporal": list(b.nontemporal),
             "autotune_ms_per_step": tune["ms_per_step"],
             "nonfinite_instances": int(np.sum(s["nonfinite"] > 0)),
-            "hbm_gbs": round(144.0 * nodes * steps / dt / 1e9, 1)}
+            "hbm_gbs": round(144.0 * nodes * steps / dt / 1e9, 1),
+            "kernel_ms_per_step": round(0.5 * pair, 4), "kernel_gbs": round(kg, 1),
+            "pattern_ms": [round(pat[0], 4), round(pat[1], 4)], "pattern_gbs": round(pg, 1),
+            "frac_of_pattern": round(kg / pg, 4)}
 
 
 def run_surrogate(count=16, cap=400_000):

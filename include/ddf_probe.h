@@ -51,6 +51,14 @@ int ddf_bandwidth_probe(int32_t kind, int32_t unroll, int32_t nontemporal, const
  * handle's earlier work.  DDF_ERR_ARG for a NULL handle, another parity or cap. */
 int ddf_pattern_probe(ddf_handle *h, int32_t parity, int32_t wg_per_cu, void *stream);
 
+/* The same for the batch b: one parity of its step's loads and stores over the tiles of
+ * its active instances, with the collision left out (same tile list, XCD map and
+ * non-temporal setting as ddf_batch_step; each value stored sign-flipped where the step
+ * stores the opposite direction, walls included).  Two calls of one parity restore the
+ * populations; the step count is not changed.  DDF_ERR_ARG for a NULL batch or another
+ * parity. */
+int ddf_batch_pattern_probe(ddf_batch *b, int32_t parity, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -146,6 +146,7 @@ SIGNATURES.update(NN_SIGNATURES)
 PROBE_COPY, PROBE_READ, PROBE_WRITE = 0, 1, 2
 SIGNATURES["ddf_bandwidth_probe"] = (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _vp, _vp, C.c_size_t, _vp])
 SIGNATURES["ddf_pattern_probe"] = (C.c_int, [_vp, C.c_int32, C.c_int32, _vp])
+SIGNATURES["ddf_batch_pattern_probe"] = (C.c_int, [_vp, C.c_int32, _vp])
 
 _lib = None
 

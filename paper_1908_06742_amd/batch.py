@@ -113,6 +113,13 @@ class Batch:
         L.check(L.lib().ddf_batch_get_tiling(self._h, *[C.byref(x) for x in v]))
         return dict(zip(("bx_max", "blocks_per_cu", "ntiles", "grid"), [x.value for x in v]))
 
+    def pattern_probe(self, parity):
+        """The batch step's memory accesses of one parity without its collision (a
+        reference for its bandwidth): swaps opposite directions in each node's slot set
+        and flips their signs, so two calls of one parity restore the populations."""
+        L.check(L.lib().ddf_batch_pattern_probe(self._h, int(parity), _stream_ptr(self.stream)))
+        return self
+
     def set_graph(self, steps_per_graph):
         L.check(L.lib().ddf_batch_set_graph(self._h, int(steps_per_graph)))
 

@@ -21,6 +21,7 @@
 #include <utility>
 #include <vector>
 
+#include "../../include/ddf_probe.h"
 #include "ddf_kernels.hpp"
 
 using namespace ddf;
@@ -77,6 +78,65 @@ __global__ __launch_bounds__(kThreads) void k_batch_step(S *__restrict__ f, S *_
         int x, y;
         if (inst_node(D, tr.tile, x, y))
             step_node<S, SCALAR, true, true, ODD, false, LY_ROW, NT>(f + D.off, g + D.off, D.L, D.P, x, y, t);
+    }
+}
+
+// The batch step's memory accesses with the collision left out (the batch counterpart
+// of ddf_pattern_probe): same tile list, XCD map and non-temporal policy; each value is
+// stored with its top (sign) bit flipped where the step stores the opposite direction,
+// which is the slot the step loaded as that direction (walls included).  Two launches of
+// one parity restore the populations.
+template <class S>
+__device__ __forceinline__ S flip_top_bit(S v)
+{
+    if constexpr (sizeof(S) == 8) {
+        uint64_t u;
+        __builtin_memcpy(&u, &v, 8);
+        u ^= (uint64_t)1 << 63;
+        __builtin_memcpy(&v, &u, 8);
+    } else if constexpr (sizeof(S) == 4) {
+        uint32_t u;
+        __builtin_memcpy(&u, &v, 4);
+        u ^= 0x80000000u;
+        __builtin_memcpy(&v, &u, 4);
+    } else {
+        uint16_t u;
+        __builtin_memcpy(&u, &v, 2);
+        u ^= 0x8000u;
+        __builtin_memcpy(&v, &u, 2);
+    }
+    return v;
+}
+
+template <class S, bool ODD, bool NT>
+__global__ __launch_bounds__(kThreads) void k_batch_pattern(S *__restrict__ f, S *__restrict__ g,
+                                                            const InstDesc<typename Codec<S>::R> *__restrict__ inst,
+                                                            const TileRef *__restrict__ tiles, const int ntiles)
+{
+    const int per = gridDim.x >> 3;
+    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+    const int t0 = (int)((int64_t)ntiles * xcd / 8), t1 = (int)((int64_t)ntiles * (xcd + 1) / 8);
+    for (int k = t0 + local; k < t1; k += per) {
+        const TileRef tr = tiles[k];
+        const auto &D = inst[tr.inst];
+        int x, y;
+        if (!inst_node(D, tr.tile, x, y)) continue;
+        S *fi = f + D.off, *gi = g + D.off;
+        int pa[9];
+        int64_t c[9];
+        S vf[9], vg[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            c[a] = logical_cell<true, ODD, LY_ROW>(D.L, x, y, a, pa[a]);
+            vf[a] = ld_pop<NT>(&elem<false>(fi, D.L, pa[a], c[a]));
+        }
+#pragma unroll
+        for (int a = 0; a < 9; ++a) vg[a] = ld_pop<NT>(&elem<false>(gi, D.L, pa[a], c[a]));
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            st_pop<NT>(&elem<false>(fi, D.L, pa[opp(a)], c[opp(a)]), flip_top_bit(vf[a]));
+            st_pop<NT>(&elem<false>(gi, D.L, pa[opp(a)], c[opp(a)]), flip_top_bit(vg[a]));
+        }
     }
 }
 
@@ -655,6 +715,29 @@ int ddf_batch_set_graph(ddf_batch *b, int32_t steps_per_graph)
     }
     drop_graph(b);
     b->graph_steps = steps_per_graph;
+    return DDF_OK;
+}
+
+int ddf_batch_pattern_probe(ddf_batch *b, int32_t parity, void *stream)
+{
+    if (!b) return fail(DDF_ERR_ARG, "batch pattern probe: batch is NULL");
+    if (parity != 0 && parity != 1) return fail(DDF_ERR_ARG, "batch pattern probe: parity must be 0 (even) or 1 (odd)");
+    if (b->nstep_tiles == 0) return DDF_OK;
+    hipStream_t st = (hipStream_t)stream;
+    with_storage(b->storage, [&](auto *tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        using R = typename Codec<S>::R;
+        const auto *inst = (const InstDesc<R> *)b->d_inst;
+#define DDF_BP(O_, N_)                                                                                              \
+        hipLaunchKernelGGL((k_batch_pattern<S, O_, N_>), dim3(b->grid), dim3(kThreads), 0, st, (S *)b->f, (S *)b->g, inst, \
+                           b->d_step_tiles, b->nstep_tiles)
+        if (parity) { if (b->nt[1]) DDF_BP(true, true); else DDF_BP(true, false); }
+        else { if (b->nt[0]) DDF_BP(false, true); else DDF_BP(false, false); }
+#undef DDF_BP
+        return 0;
+    });
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DDF_ERR_HIP, std::string("batch pattern probe launch: ") + hipGetErrorString(e));
     return DDF_OK;
 }
 

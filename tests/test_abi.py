@@ -223,6 +223,8 @@ def test_pattern_probe_rejects_invalid_arguments_before_any_launch():
     lib = L.lib()
     assert lib.ddf_pattern_probe(None, 0, 0, None) == L.DDF_ERR_ARG
     assert "NULL" in lib.ddf_last_error().decode()
+    assert lib.ddf_batch_pattern_probe(None, 0, None) == L.DDF_ERR_ARG
+    assert "NULL" in lib.ddf_last_error().decode()
     for pr, cases in ((W.taylor_green_problem(16), ((2, 0, L.DDF_ERR_ARG, "parity"), (1, 4, L.DDF_ERR_ARG, "per CU"),
                                                     (0, -1, L.DDF_ERR_ARG, "per CU"))),
                       (W.Problem(nx=16, ny=16, periodic_x=False, periodic_y=False), ((-1, 1, L.DDF_ERR_ARG, "parity"),))):

@@ -158,3 +158,51 @@ def test_pattern_probe_with_walls_reflects_where_the_step_does(storage, nx, ny, 
     lat.pattern_probe(1, 0)
     f2, g2 = pops()
     assert same(f2, f0) and same(g2, g0)
+
+
+@pytest.mark.parametrize("bx_max", [0, 64])     # flat tiles of 512 nodes; 64-wide rectangular tiles
+def test_batch_pattern_probe_matches_the_model_on_every_instance(bx_max):
+    from paper_1908_06742_amd.batch import Batch
+    print(f"case: batch pattern probe tiles {bx_max}", flush=True)
+    probs = [W.cavity_problem(40, 500.0, 0.08, storage="f32"),
+             W.Problem(nx=64, ny=20, periodic_x=True, periodic_y=False, storage="f32"),
+             W.cavity_problem(37, 900.0, 0.06, storage="f32")]
+    b = Batch(probs, device=DEV)
+    b.init([W.rest_fields(p.nx, p.ny) for p in probs])
+    b.set_tiling(bx_max, 0)
+    g = torch.Generator().manual_seed(11 + bx_max)
+    views = []
+    for i, p in enumerate(probs):
+        po, fo = C.c_int64(), C.c_int64()
+        L.check(L.lib().ddf_batch_offsets(b._h, i, C.byref(po), C.byref(fo)))
+        plane = (p.nx * p.ny + 63) // 64 * 64
+        inst = []
+        for buf in (b.pop_f, b.pop_g):
+            flat = buf[po.value:po.value + 4 * 9 * plane].view(torch.float32)
+            inst.append(flat.view(9, plane)[:, :p.nx * p.ny].view(9, p.ny, p.nx))
+        views.append(inst)
+        for v in inst:
+            v.copy_(torch.randn(v.shape, generator=g).to(DEV))
+    torch.cuda.synchronize()
+    start = [[v.cpu().clone() for v in inst] for inst in views]
+
+    def same(a, b_):
+        return torch.equal(a.contiguous().view(torch.int32), torch.as_tensor(b_).contiguous().view(torch.int32))
+
+    b.pattern_probe(0)
+    torch.cuda.synchronize()
+    for inst, s0 in zip(views, start):
+        for v, v0 in zip(inst, s0):
+            assert same(v.cpu(), -v0[OPP])
+    b.pattern_probe(0)
+    b.pattern_probe(1)
+    torch.cuda.synchronize()
+    for p, inst, s0 in zip(probs, views, start):
+        for v, v0 in zip(inst, s0):
+            assert same(v.cpu(), _odd_pattern_model(v0.numpy(), p.periodic_x, p.periodic_y))
+    b.pattern_probe(1)
+    torch.cuda.synchronize()
+    for inst, s0 in zip(views, start):
+        for v, v0 in zip(inst, s0):
+            assert same(v.cpu(), v0)
+    assert b.step_count == 0
