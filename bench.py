@@ -440,6 +440,45 @@ def unet_flops_per_sample(H=256, W=256, base=32, levels=4):
     return fwd, fwd + dgrad + fwd
 
 
+def unet_bound_us(batch=8, H=256, W=256, base=32, levels=4):
+    """Lower bound on one training iteration and on one forward pass of the surrogate
+    U-Net (microseconds): every kernel at the larger of its matrix-core time at the dense
+    BF16 peak and its HBM time at 8 TB/s for the bytes it must move (activations in and
+    out once, as the kernels store them: channels padded to 32, BF16; weights, Adam
+    state and the loss target once), summed over the kernels of an iteration."""
+    from paper_1908_06742_amd.surrogate import layer_table, _pad
+
+    pk, bw = BF16_PEAK_TFLOPS * 1e12, HBM_PEAK_GBS * 1e9
+    t = lambda fl, by: 1e6 * max(fl / pk, by / bw)   # noqa: E731
+    fwd = train = 0.0
+    nparam = 0
+    ch = [base * 2 ** k for k in range(levels)]
+    for name, ci, co, _ in layer_table(base, levels):
+        lvl = 0 if name == "head" else int(name[3])
+        cip, cop = (32 if name == "enc0a" else _pad(ci)), _pad(co)
+        px = batch * (H >> lvl) * (W >> lvl)
+        fl = 2.0 * 9 * cip * cop * px
+        nparam += 9 * cip * cop + cop
+        f = t(fl, 2 * px * (cip + cop))
+        fwd += f
+        train += f + t(fl, 2 * px * (cip + cop))                 # weight gradient: input and dY
+        if name != "enc0a":
+            train += t(fl, 2 * px * (cop + 2 * cip))             # data gradient: dY, mask, dX
+    for k in range(1, levels):                                   # pooling, upsampling, adjoints
+        hi, lo, c = batch * (H >> (k - 1)) * (W >> (k - 1)), batch * (H >> k) * (W >> k), ch[k - 1]
+        fwd += t(0, 2 * c * (hi + lo))
+        train += t(0, 2 * c * (hi + lo)) + t(0, 2 * c * (3 * hi + lo))
+        cu = ch[k]
+        fwd += t(0, 2 * cu * (hi + lo))
+        train += t(0, 2 * cu * (hi + lo)) * 2
+    px0 = batch * H * W
+    inputs = t(0, 2 * 32 * px0)
+    loss = t(0, px0 * (2 * 32 + 16 + 2 * 32))                    # head, target; dY of the head
+    adam = t(0, nparam * (4 * 4 + 3 * 4))                        # w, g, m, v in; w, m, v out
+    cast = t(0, nparam * (4 + 2 * 2))
+    return {"train_us": round(train + inputs + loss + adam + cast, 1), "forward_us": round(fwd + inputs, 1)}
+
+
 def run_unet(batch=8, iters=50):
     """One Adam training iteration of the surrogate U-Net on batch x 256^2 (forward, loss,
     backward, Adam, BF16 weight casts), timed with HIP events; and the forward alone."""
@@ -470,13 +509,19 @@ def run_unet(batch=8, iters=50):
     net.inputs(re, u, H, W)
     t_fwd = timed(lambda: net.forward(batch, H, W), iters)
     f_fwd, f_train = unet_flops_per_sample(H, W)
+    bound = unet_bound_us(batch, H, W)
     tf_train = batch * f_train / (t_train * 1e-3) / 1e12
     tf_fwd = batch * f_fwd / (t_fwd * 1e-3) / 1e12
     return {"workload": f"surrogate U-Net (4 levels, base 32, BF16 MFMA), batch {batch} x 256^2",
             "ms_per_train_iter": round(t_train, 3), "train_tflops": round(tf_train, 1),
             "ms_per_forward": round(t_fwd, 3), "forward_tflops": round(tf_fwd, 1),
             "peak_tflops": BF16_PEAK_TFLOPS, "train_frac": round(tf_train / BF16_PEAK_TFLOPS, 4),
-            "forward_frac": round(tf_fwd / BF16_PEAK_TFLOPS, 4)}
+            "forward_frac": round(tf_fwd / BF16_PEAK_TFLOPS, 4),
+            # the iteration against the sum of its kernels' matrix-core or HBM bounds
+            "bound_ms_per_train_iter": round(bound["train_us"] / 1e3, 3),
+            "frac_of_bound_train": round(bound["train_us"] / 1e3 / t_train, 4),
+            "bound_ms_per_forward": round(bound["forward_us"] / 1e3, 3),
+            "frac_of_bound_forward": round(bound["forward_us"] / 1e3 / t_fwd, 4)}
 
 
 def cpu_baseline(budget_s=12.0):

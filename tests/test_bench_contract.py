@@ -52,3 +52,21 @@ def test_unet_flop_count():
     assert abs(fwd - 23.56e9) < 0.01e9
     assert train == 3 * fwd - first
     assert abs(train - 69.46e9) < 0.01e9
+
+
+def test_unet_bound_is_at_least_the_matrix_core_time_and_the_traffic_time():
+    # the bound sums, per kernel, the larger of matrix-core time and HBM time: it can be
+    # no less than either summed alone, and the forward pass is part of the iteration
+    b = bench.unet_bound_us(batch=8)
+    fwd, train = bench.unet_flops_per_sample()
+    mfma_train_us = 8 * train / (bench.BF16_PEAK_TFLOPS * 1e12) * 1e6
+    mfma_fwd_us = 8 * fwd / (bench.BF16_PEAK_TFLOPS * 1e12) * 1e6
+    assert b["train_us"] >= mfma_train_us and b["forward_us"] >= mfma_fwd_us
+    assert b["forward_us"] < b["train_us"]
+    # the level-0 activations alone: 8 x 256^2 pixels x 32 channels in BF16, read and
+    # written by the two encoder convolutions at 8 TB/s
+    assert b["forward_us"] > 2 * (8 * 256 * 256 * 64 * 2) / (bench.HBM_PEAK_GBS * 1e9) * 1e6
+    # doubling the batch doubles every per-pixel term; Adam and the weight casts stay
+    b2 = bench.unet_bound_us(batch=16)
+    assert abs(b2["forward_us"] - 2 * b["forward_us"]) < 0.2
+    assert 1.9 * b["train_us"] < b2["train_us"] < 2 * b["train_us"]
