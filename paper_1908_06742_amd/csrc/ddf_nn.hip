@@ -968,6 +968,38 @@ struct CastTable {
     int n;
 };
 
+// Tiled form for layers whose padded channel counts are multiples of 32: one workgroup
+// per (layer, tap, 32 output channels, 32 input channels) tile, which it reads and
+// writes to wf along the input channels, then writes transposed to wd along the output
+// channels through LDS, so both stores are coalesced (the per-element form scatters its
+// wd stores Cout_p elements apart).  tstart[k] = start[k] / 1024.
+__global__ __launch_bounds__(256) void k_cast_weight_tiles(const CastTable t)
+{
+    __shared__ float tile[32][33];
+    const int64_t b = blockIdx.x;
+    int k = 0;
+    while (k + 1 < t.n && b >= t.start[k + 1] / 1024) ++k;
+    const ddf_nn_cast_layer &L = t.l[k];
+    const int local = (int)(b - t.start[k] / 1024);
+    const int nci = L.Cin_p / 32, nco = L.Cout_p / 32;
+    const int cit = local % nci, cot = (local / nci) % nco, tap = local / (nci * nco);
+    const int lane = threadIdx.x & 31, row = threadIdx.x >> 5;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int co = 32 * cot + row + 8 * r, ci = 32 * cit + lane;
+        const float v = (co < L.Cout && ci < L.Cin) ? L.w[((int64_t)tap * L.Cout + co) * L.Cin + ci] : 0.0f;
+        ((__bf16 *)L.wf)[((int64_t)tap * L.Cout_p + co) * L.Cin_p + ci] = (__bf16)v;
+        tile[row + 8 * r][lane] = v;
+    }
+    if (!L.wd) return;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int ci = 32 * cit + row + 8 * r, co = 32 * cot + lane;
+        ((__bf16 *)L.wd)[((int64_t)(8 - tap) * L.Cin_p + ci) * L.Cout_p + co] = (__bf16)tile[lane][row + 8 * r];
+    }
+}
+
 __global__ void k_cast_weights_multi(const CastTable t)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1498,7 +1530,13 @@ int ddf_nn_cast_weights_multi(int32_t n, const ddf_nn_cast_layer *layers, void *
         t.l[k] = L;
         t.start[k + 1] = t.start[k] + (int64_t)9 * L.Cout_p * L.Cin_p;
     }
-    hipLaunchKernelGGL(k_cast_weights_multi, dim3(blocks_for(t.start[n])), dim3(256), 0, (hipStream_t)stream, t);
+    bool tiled = true;
+    for (int k = 0; k < n; ++k) tiled = tiled && layers[k].Cout_p % 32 == 0 && layers[k].Cin_p % 32 == 0;
+    if (tiled && t.start[n] / 1024 < ((int64_t)1 << 31))
+        hipLaunchKernelGGL(k_cast_weight_tiles, dim3((unsigned)(t.start[n] / 1024)), dim3(256), 0,
+                           (hipStream_t)stream, t);
+    else
+        hipLaunchKernelGGL(k_cast_weights_multi, dim3(blocks_for(t.start[n])), dim3(256), 0, (hipStream_t)stream, t);
     return check_launch();
 }
 

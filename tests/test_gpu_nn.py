@@ -152,9 +152,14 @@ def test_pool_up_slice_relu_kernels():
     assert np.array_equal(np_of(gg, x.shape), np.where(x > 0, x, 0.0))
 
 
-def test_cast_weights_multi_matches_per_layer_casts():
-    # padded and unpadded layers, one without the data-gradient copy
-    shapes = [(32, 5, 32, 32, True), (64, 32, 64, 32, True), (96, 40, 96, 64, False), (256, 256, 256, 256, True)]
+@pytest.mark.parametrize("shapes", [
+    # padded to multiples of 32 (32 x 32 tiles through LDS), one without the data-gradient copy
+    [(32, 5, 32, 32, True), (64, 32, 64, 32, True), (96, 40, 96, 64, False), (256, 256, 256, 256, True),
+     (384, 128, 384, 128, True)],
+    # other padded sizes (one element per thread)
+    [(10, 5, 12, 8, True), (64, 32, 64, 32, True), (3, 7, 3, 9, False)],
+])
+def test_cast_weights_multi_matches_per_layer_casts(shapes):
     r = np.random.default_rng(7)
     layers, ref = [], []
     for co, ci, cop, cip, with_wd in shapes:
