@@ -437,16 +437,28 @@ def test_weight_gradients_on_a_side_stream_match_one_stream(B, H):
     # kernels are the same, so three training steps (Adam and the next forward wait
     # for them) must give bit-identical gradients and weights
     W = H
-    nets = [UNet(base=32, levels=4, device=DEV, seed=5, overlap_wgrad=ov) for ov in (False, True)]
+    user = torch.cuda.Stream(device=DEV)     # a caller's own stream as the network's main stream
+    nets = [UNet(base=32, levels=4, device=DEV, seed=5, overlap_wgrad=ov, stream=st)
+            for ov, st in ((False, None), (True, None), (True, user))]
     g = torch.Generator(device=DEV).manual_seed(B)
     re = 100.0 + 4900.0 * torch.rand(B, device=DEV, generator=g)
     u = 0.05 + 0.05 * torch.rand(B, device=DEV, generator=g)
     tgt = torch.randn(B * H * W * 4, device=DEV, generator=g)
+    torch.cuda.synchronize()
     for it in range(3):
-        losses = [net.train_step(re, u, tgt, H, W, lr=1e-3).item() for net in nets]
-        assert losses[0] == losses[1], (it, losses)
-        assert torch.equal(nets[0].g, nets[1].g), it
-        assert torch.equal(nets[0].w, nets[1].w), it
+        losses = []
+        for net in nets:
+            if net.stream is None:
+                losses.append(net.train_step(re, u, tgt, H, W, lr=1e-3).item())
+            else:
+                with torch.cuda.stream(net.stream):
+                    loss = net.train_step(re, u, tgt, H, W, lr=1e-3)
+                net.stream.synchronize()
+                losses.append(loss.item())
+        assert losses[0] == losses[1] == losses[2], (it, losses)
+        for net in nets[1:]:
+            assert torch.equal(nets[0].g, net.g), it
+            assert torch.equal(nets[0].w, net.w), it
     assert nets[1]._side is not None and nets[0]._side is None
 
 
