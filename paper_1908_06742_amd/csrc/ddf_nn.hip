@@ -427,34 +427,26 @@ __device__ __forceinline__ bf16x8 tr_operand(const __bf16 *p, int row_stride)
 // CO_T x CI_T output tiles of 32 x 32, so each staged value feeds several MFMAs.  The
 // contraction runs over pixels, which NHWC keeps strided: operands come out of the
 // [pixel][channel] tiles by transpose reads (tr_operand); rows are padded by 8 elements.
-// A workgroup holds SUB sub-groups with their own staging buffers; sub-group s takes
-// blocks b0 + s, b0 + s + SUB, ... of the workgroup's chunk, and at the end the sub-groups'
-// accumulators are added in LDS in the order s = 0, 1, ..., so a chunk writes one set
-// of partials for SUB times the pixels (the partials are written once and read once by
-// the split-K sum).  part[chunk * cstride + (tap Cout + co) Cin + ci] receives the
-// chunk's sums (tap = 3 (dy + 1) + dx + 1).  The workgroups of the first input-channel
+// part[chunk * cstride + (tap Cout + co) Cin + ci] receives the chunk's sums
+// (tap = 3 (dy + 1) + dx + 1).  The workgroups of the first input-channel
 // tile also sum the staged output gradient over the chunk's pixels into
 // bpart[chunk * cstride + co] (bias gradient), in a fixed order.
-template <int PB, int CO_T, int CI_T, int SUB = 1>
-__global__ __launch_bounds__(192 * SUB) void k_wgrad_lds(const __bf16 *__restrict__ in, int N, int H, int W, int Cin,
+template <int PB, int CO_T, int CI_T>
+__global__ __launch_bounds__(192) void k_wgrad_lds(const __bf16 *__restrict__ in, int N, int H, int W, int Cin,
                                                          int in_cs, int in_co, const __bf16 *__restrict__ dout, int Cout,
                                                          int d_cs, int blocks_per_chunk, float *__restrict__ part,
                                                          float *__restrict__ bpart, int64_t cstride)
 {
     constexpr int XS = 32 * CI_T + 8;
     constexpr int DS = 32 * CO_T + 8;
-    constexpr int NT = 192 * SUB;
-    constexpr size_t XB = (size_t)SUB * 3 * (PB + 2) * XS * 2, DB = (size_t)SUB * PB * DS * 2;
-    constexpr size_t RB = SUB > 1 ? (size_t)192 * 16 * CO_T * CI_T * 4 : 0;   // one kernel column of a sub-group
-    constexpr size_t SB = XB + DB > RB ? XB + DB : RB;
-    __shared__ __attribute__((aligned(16))) unsigned char smem[SB];
-    __shared__ float bred[NT][8];
+    constexpr size_t XB = (size_t)3 * (PB + 2) * XS * 2, DB = (size_t)PB * DS * 2;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[XB + DB];
+    __shared__ float bred[192][8];
     typedef __bf16 XRow[PB + 2][XS];
     typedef __bf16 DRow[DS];
-    const int tid = threadIdx.x, sub = tid / 192, t = tid - 192 * sub;
-    const int lane = t & 63, r = t >> 6;
-    XRow *xs = (XRow *)smem + 3 * sub;                   // this sub-group's three input rows
-    DRow *ds = (DRow *)(smem + XB) + PB * sub;           // and output-gradient block
+    const int t = threadIdx.x, lane = t & 63, r = t >> 6;
+    XRow *xs = (XRow *)smem;              // the three input rows
+    DRow *ds = (DRow *)(smem + XB);       // and the output-gradient block
     const int m = lane & 31, half = lane >> 5;
     const int tiles_ci = Cin / (32 * CI_T);
     const int ci0 = (blockIdx.x % tiles_ci) * 32 * CI_T, co0 = (blockIdx.x / tiles_ci) * 32 * CO_T;
@@ -479,10 +471,8 @@ __global__ __launch_bounds__(192 * SUB) void k_wgrad_lds(const __bf16 *__restric
             for (int b = 0; b < CI_T; ++b)
 #pragma unroll
                 for (int j = 0; j < 16; ++j) acc[dx][a][b][j] = 0.0f;
-    // Staging is software-pipelined: the global loads of a sub-group's next block are
-    // issued into registers before the MFMAs of its current block and written to LDS
-    // after them.  Every sub-group makes the same number of turns (blocks past the chunk
-    // stage zeros), so the workgroup's barriers match.
+    // Staging is software-pipelined: the global loads of the next block are issued into
+    // registers before the MFMAs of the current block and written to LDS after them.
     constexpr int XV = 3 * (PB + 2) * 4 * CI_T;   // 16-byte input vectors per block
     constexpr int DV = PB * 4 * CO_T;             // 16-byte output-gradient vectors per block
     constexpr int NXV = (XV + 191) / 192, NDV = (DV + 191) / 192;
@@ -510,10 +500,8 @@ __global__ __launch_bounds__(192 * SUB) void k_wgrad_lds(const __bf16 *__restric
             if (ok && v < DV) dr[i] = load8(dout + (row * W + x0 + px) * d_cs + co0 + 8 * c8);
         }
     };
-    const int64_t turns = (b1 - b0 + SUB - 1) / SUB;
-    if (turns > 0) fetch(b0 + sub);
-    for (int64_t k = 0; k < turns; ++k) {
-        const int64_t blk = b0 + k * SUB + sub;
+    if (b0 < b1) fetch(b0);
+    for (int64_t blk = b0; blk < b1; ++blk) {
 #pragma unroll
         for (int i = 0; i < NXV; ++i) {
             const int v = t + 192 * i;
@@ -527,14 +515,14 @@ __global__ __launch_bounds__(192 * SUB) void k_wgrad_lds(const __bf16 *__restric
             const int c8 = v % (4 * CO_T), px = v / (4 * CO_T);
             if (v < DV) {
                 *(bf16x8 *)&ds[px][8 * c8] = dr[i];
-                if (bias) {   // blocks past the chunk staged zeros
+                if (bias) {
 #pragma unroll
                     for (int j = 0; j < 8; ++j) bsum[j] += (float)dr[i][j];
                 }
             }
         }
         __syncthreads();
-        if (k + 1 < turns) fetch(blk + SUB);
+        if (blk + 1 < b1) fetch(blk + 1);
 #pragma unroll
         for (int k0 = 0; k0 < PB; k0 += 16) {
             bf16x8 a[CO_T];
@@ -555,55 +543,224 @@ __global__ __launch_bounds__(192 * SUB) void k_wgrad_lds(const __bf16 *__restric
     }
     if (bias) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) bred[tid][i] = bsum[i];
+        for (int i = 0; i < 8; ++i) bred[t][i] = bsum[i];
         __syncthreads();
-        if (tid < 32 * CO_T) {
-            const int c8 = tid >> 3, i = tid & 7;
+        if (t < 32 * CO_T) {
+            const int c8 = t >> 3, i = t & 7;
             float s8 = 0.0f;
-            for (int u = c8; u < NT; u += 4 * CO_T) s8 += bred[u][i];
+            for (int u = c8; u < 192; u += 4 * CO_T) s8 += bred[u][i];
             bpart[(int64_t)ck * cstride + co0 + 8 * c8 + i] = s8;
         }
     }
-    if constexpr (SUB > 1) {
-        // sub-group 0 adds the others' accumulators, one kernel column at a time, in the
-        // order 1, 2, ...: thread t of sub-group s passes its values through red[t][...]
-        float *red = (float *)smem;
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx)
-            for (int s2 = 1; s2 < SUB; ++s2) {
-                __syncthreads();   // the staging buffers (or the previous column) are free
-                if (sub == s2) {
+    for (int dx = 0; dx < 3; ++dx) {
+        float *o = part + (int64_t)ck * cstride + ((int64_t)(3 * r + dx) * Cout) * Cin;
 #pragma unroll
-                    for (int tt = 0; tt < CO_T; ++tt)
+        for (int tt = 0; tt < CO_T; ++tt)
 #pragma unroll
-                        for (int u = 0; u < CI_T; ++u)
+            for (int u = 0; u < CI_T; ++u)
 #pragma unroll
-                            for (int j = 0; j < 16; ++j) red[((tt * CI_T + u) * 16 + j) * 192 + t] = acc[dx][tt][u][j];
+                for (int j = 0; j < 16; ++j) {
+                    const int co = co0 + 32 * tt + 8 * (j >> 2) + 4 * half + (j & 3);
+                    o[(int64_t)co * Cin + ci0 + 32 * u + m] = acc[dx][tt][u][j];
                 }
-                __syncthreads();
-                if (sub == 0) {
+    }
+}
+
+// Row-streaming weight gradient for one 32 x 32 (output channel, input channel) tile per
+// workgroup.  dW[dy][dx][co][ci] = sum over output pixels q of dout[q][co] in[q + (dy, dx)][ci]
+// is summed as sum over input pixels p of dout[p - (0, dx)][co] in[p + (dy, 0)][ci]: across
+// the blocks of a row p covers [0, W) exactly, and the terms the substitution adds or drops
+// have a zero factor (dout outside the image, or the convolution's zero padding).  A
+// sub-group of four wavefronts walks a strip of output rows y0 .. y1-1 of one PB-pixel
+// column; per row it stages the output-gradient row with a one-pixel halo and the next input
+// row, which joins the two before it in a ring of three, so every input row is read from
+// memory once per strip (plus two rows of halo).  Wavefront w of the sub-group takes the
+// 16-pixel steps k0 = 16 (w + 4 i) of the row; per step it reads the three dx-shifted
+// output-gradient operands and the three input rows' operands once and issues the nine tap
+// products (A = output gradient, B = input, both by transpose reads).  The next row's loads
+// are in flight during the current row's products, and the strip's first rows are requested
+// together.  At the end the four wavefronts' sums are added in LDS in wavefront order, one
+// kernel row (dy) at a time, and go to part[strip * cstride + (tap Cout + co) Cin + ci]; the
+// workgroups of the first input-channel tile also write the strip's output-gradient sums to
+// bpart (bias gradient).  The 1-D grid is split into eight contiguous ranges, one per XCD, so
+// the workgroups of one strip (and its neighbours) share an L2.  Two workgroups of four
+// wavefronts fit a CU (at most 256 registers per lane).
+template <int PB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_wgrad_roll(
+    const __bf16 *__restrict__ in, int N, int H, int W, int Cin, int in_cs, int in_co, const __bf16 *__restrict__ dout,
+    int Cout, int d_cs, int rows_per_strip, float *__restrict__ part, float *__restrict__ bpart, int64_t cstride)
+{
+    static_assert(PB % 64 == 0, "four wavefronts of 16-pixel steps");
+    constexpr int KPW = PB / 64;                       // steps per wavefront per row
+    constexpr int RS = 40;                             // padded row stride (elements)
+    constexpr int NDV = ((PB + 2) * 4 + 255) / 256;    // 16-byte output-gradient vectors per thread
+    constexpr int NIV = (PB * 4 + 255) / 256;          // 16-byte input vectors per thread
+    constexpr size_t STAGE = (size_t)(3 * PB + PB + 2) * RS * 2;
+    constexpr size_t RED = (size_t)3 * 4 * 64 * 16 * 4;   // three taps x four wavefronts
+    __shared__ __attribute__((aligned(16))) unsigned char smem[STAGE > RED ? STAGE : RED];
+    __shared__ float bred[256][8];
+    typedef __bf16 Row[RS];
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63, m = lane & 31, half = lane >> 5;
+    Row *is = (Row *)smem;         // input ring: slot s holds rows s PB .. s PB + PB - 1
+    Row *ds = is + 3 * PB;         // output-gradient row, pixels x0 - 1 .. x0 + PB
+    const int tiles_ci = Cin / 32, tiles = tiles_ci * (Cout / 32);
+    const int bpr = W / PB, spc = (H + rows_per_strip - 1) / rows_per_strip;
+    const int64_t total = (int64_t)tiles * N * bpr * spc;
+    // XCD-contiguous order: block L runs on XCD L mod 8 and takes the (L / 8)-th item of
+    // that XCD's range
+    const int64_t L = blockIdx.x, q8 = total / 8, r8 = total % 8, x8 = L % 8;
+    const int64_t item = x8 * q8 + (x8 < r8 ? x8 : r8) + L / 8;
+    const int tile = (int)(item % tiles);
+    const int64_t strip = item / tiles, col = strip / spc;
+    const int ci0 = (tile % tiles_ci) * 32, co0 = (tile / tiles_ci) * 32;
+    const bool bias = bpart != nullptr && tile % tiles_ci == 0;
+    const int y0 = (int)(strip % spc) * rows_per_strip;
+    const int y1 = y0 + rows_per_strip < H ? y0 + rows_per_strip : H;
+    const int n = (int)(col / bpr), x0 = (int)(col % bpr) * PB;
+    const int tr_row = 8 * (lane >> 5) + ((lane & 15) >> 2);
+    const int tr_col = 16 * ((lane >> 4) & 1) + 4 * (lane & 3);
+    float bsum[8];
 #pragma unroll
-                    for (int tt = 0; tt < CO_T; ++tt)
+    for (int i = 0; i < 8; ++i) bsum[i] = 0.0f;
+    f32x16 acc[3][3];
 #pragma unroll
-                        for (int u = 0; u < CI_T; ++u)
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-                            for (int j = 0; j < 16; ++j) acc[dx][tt][u][j] += red[((tt * CI_T + u) * 16 + j) * 192 + t];
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc[a][b][j] = 0.0f;
+    bf16x8 dr[NDV], ir[NIV];
+    // input row yy into v (zeros outside the image)
+    auto fetch_in = [&](bf16x8 (&v)[NIV], int yy) {
+#pragma unroll
+        for (int i = 0; i < NIV; ++i) {
+            const int e = t + 256 * i;
+            v[i] = zero8();
+            if (e < PB * 4 && yy >= 0 && yy < H)
+                v[i] = load8(in + (((int64_t)n * H + yy) * W + x0 + (e >> 2)) * in_cs + in_co + ci0 + 8 * (e & 3));
+        }
+    };
+    auto store_in = [&](const bf16x8 (&v)[NIV], int slot) {
+#pragma unroll
+        for (int i = 0; i < NIV; ++i) {
+            const int e = t + 256 * i;
+            if (e < PB * 4) *(bf16x8 *)&is[slot * PB + (e >> 2)][8 * (e & 3)] = v[i];
+        }
+    };
+    // turn y: the output-gradient row y with its halo and the input row y + 1
+    auto fetch = [&](int y) {
+#pragma unroll
+        for (int i = 0; i < NDV; ++i) {
+            const int e = t + 256 * i;
+            const int xx = x0 - 1 + (e >> 2);
+            dr[i] = zero8();
+            if (e < (PB + 2) * 4 && xx >= 0 && xx < W)
+                dr[i] = load8(dout + (((int64_t)n * H + y) * W + xx) * d_cs + co0 + 8 * (e & 3));
+        }
+        fetch_in(ir, y + 1);
+    };
+    {   // prologue: input rows y0 - 1 and y0 into slots 0 and 1, the first turn's rows in flight
+        bf16x8 p0[NIV], p1[NIV];
+        fetch_in(p0, y0 - 1);
+        fetch_in(p1, y0);
+        fetch(y0);
+        store_in(p0, 0);
+        store_in(p1, 1);
+    }
+    for (int y = y0, k = 0; y < y1; ++y, ++k) {
+        // rows y - 1, y, y + 1 sit in slots k, k + 1, k + 2 (mod 3)
+        const int s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
+#pragma unroll
+        for (int i = 0; i < NDV; ++i) {
+            const int e = t + 256 * i;
+            if (e < (PB + 2) * 4) {
+                *(bf16x8 *)&ds[e >> 2][8 * (e & 3)] = dr[i];
+                if (bias && (e >> 2) >= 1 && (e >> 2) <= PB) {   // the halo belongs to other columns
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) bsum[j] += (float)dr[i][j];
                 }
             }
+        }
+        store_in(ir, s2);
+        __syncthreads();
+        if (y + 1 < y1) fetch(y + 1);
+#pragma unroll
+        for (int kk = 0; kk < KPW; ++kk) {
+            const int k0 = 16 * (w + 4 * kk);
+            bf16x8 a[3], b[3];
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) a[dx] = tr_operand(&ds[k0 + 2 - dx + tr_row][tr_col], RS);
+            b[0] = tr_operand(&is[s0 * PB + k0 + tr_row][tr_col], RS);
+            b[1] = tr_operand(&is[s1 * PB + k0 + tr_row][tr_col], RS);
+            b[2] = tr_operand(&is[s2 * PB + k0 + tr_row][tr_col], RS);
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+                    acc[dy][dx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[dx], b[dy], acc[dy][dx], 0, 0, 0);
+        }
+        __syncthreads();
     }
-    if (sub == 0) {
+    if (bias) {
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-            float *o = part + (int64_t)ck * cstride + ((int64_t)(3 * r + dx) * Cout) * Cin;
+        for (int i = 0; i < 8; ++i) bred[t][i] = bsum[i];
+    }
+    // the four wavefronts' sums, one kernel row at a time: wavefront u < 3 owns tap (dy, u)
+    float *red = (float *)smem;   // [u][wavefront][j / 4][lane][4]
 #pragma unroll
-            for (int tt = 0; tt < CO_T; ++tt)
+    for (int dy = 0; dy < 3; ++dy) {
+        if (dy) __syncthreads();   // the previous row's owners have read red
 #pragma unroll
-                for (int u = 0; u < CI_T; ++u)
+        for (int u = 0; u < 3; ++u)
+            if (u != w) {
 #pragma unroll
-                    for (int j = 0; j < 16; ++j) {
-                        const int co = co0 + 32 * tt + 8 * (j >> 2) + 4 * half + (j & 3);
-                        o[(int64_t)co * Cin + ci0 + 32 * u + m] = acc[dx][tt][u][j];
+                for (int q = 0; q < 4; ++q) {
+                    const float4 v4 = {acc[dy][u][4 * q], acc[dy][u][4 * q + 1], acc[dy][u][4 * q + 2],
+                                       acc[dy][u][4 * q + 3]};
+                    *(float4 *)&red[(((u * 4 + w) * 4 + q) * 64 + lane) * 4] = v4;
+                }
+            }
+        __syncthreads();
+        if (w < 3) {
+            f32x16 sum;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) sum[j] = 0.0f;
+#pragma unroll
+            for (int w2 = 0; w2 < 4; ++w2) {
+                if (w2 == w) {
+#pragma unroll
+                    for (int u = 0; u < 3; ++u)
+                        if (u == w) {
+#pragma unroll
+                            for (int j = 0; j < 16; ++j) sum[j] += acc[dy][u][j];
+                        }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float4 v4 = *(const float4 *)&red[(((w * 4 + w2) * 4 + q) * 64 + lane) * 4];
+                        sum[4 * q] += v4.x;
+                        sum[4 * q + 1] += v4.y;
+                        sum[4 * q + 2] += v4.z;
+                        sum[4 * q + 3] += v4.w;
                     }
+                }
+            }
+            float *o = part + strip * cstride + ((int64_t)(3 * dy + w) * Cout) * Cin;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int co = co0 + 8 * (j >> 2) + 4 * half + (j & 3);
+                o[(int64_t)co * Cin + ci0 + m] = sum[j];
+            }
+        }
+    }
+    if (bias) {
+        __syncthreads();
+        if (t < 32) {
+            const int c8 = t >> 3, i = t & 7;
+            float s8 = 0.0f;
+            for (int u = c8; u < 256; u += 4) s8 += bred[u][i];
+            bpart[strip * cstride + co0 + 8 * c8 + i] = s8;
         }
     }
 }
@@ -1124,6 +1281,9 @@ constexpr int64_t kWgradWaves = 8192;    // target single-wave workgroups of the
 #define DDF_WGRAD_PART_FRAC 1.0
 #endif
 constexpr int64_t kWgradGroups = DDF_WGRAD_GROUPS;
+// row-streaming weight gradient: at most this many workgroups where strips of 8 or more
+// rows allow it
+constexpr int64_t kWgradRollBlocks = 512;
 constexpr double kWgradPartFrac = DDF_WGRAD_PART_FRAC;
 
 int check_launch()
@@ -1207,39 +1367,49 @@ namespace {
 
 // How ddf_nn_conv3x3_wgrad splits its work; the workspace size follows from it.
 struct WgradPlan {
+    bool roll;             // row-streaming kernel (rows of W % 64 == 0 pixels)
     bool lds;              // LDS-staged kernel (rows of W % 16 == 0 pixels)
-    int pb, co_t, ci_t;    // its pixel block and tile multiples
-    int sub;               // three-wavefront sub-groups per workgroup
-    int64_t nchunk;        // split-K chunks (partials)
-    int64_t per_chunk;     // pixel blocks (LDS kernel) or pixels (gather kernel) per chunk
+    int pb, co_t, ci_t;    // pixel block, and the LDS-staged kernel's tile multiples
+    int64_t nchunk;        // split-K chunks (partials): strips of the row-streaming kernel
+    int64_t per_chunk;     // output rows (row-streaming kernel), pixel blocks (LDS-staged
+                           // kernel) or pixels (gather kernel) per chunk
 };
 
 WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout)
 {
     WgradPlan P{};
     const int64_t npix = (int64_t)N * H * W;
-    P.pb = W % 64 == 0 ? 64 : (W % 32 == 0 ? 32 : (W % 16 == 0 ? 16 : 0));
+    if (W % 64 == 0) {
+        // Strips of 8, 16, 32, ... rows: the shortest that leave at most kWgradRollBlocks
+        // workgroups (two per CU).  At batch 8 this is the fastest strip length measured
+        // for every surrogate layer at widths 64 to 256 (32 -> 32 at 256^2: 8 rows, 512
+        // workgroups; 384 -> 128 at 64^2: 64 rows, 384): more and shorter strips add
+        // partials and per-strip start-up, fewer leave CUs idle.
+        P.roll = true;
+        P.pb = W % 128 == 0 ? 128 : 64;
+        const int64_t tiles = (int64_t)(Cin / 32) * (Cout / 32), cols = (int64_t)N * (W / P.pb);
+        int64_t rows = 8;
+        while (rows < H && cols * ((H + rows - 1) / rows) * tiles > kWgradRollBlocks) rows *= 2;
+        P.per_chunk = std::min<int64_t>(rows, H);
+        P.nchunk = cols * ((H + P.per_chunk - 1) / P.per_chunk);
+        return P;
+    }
+    P.pb = W % 32 == 0 ? 32 : (W % 16 == 0 ? 16 : 0);
     P.lds = P.pb > 0;
     if (P.lds) {
         // Two output-channel tiles per wavefront where there are pixels enough to fill the
-        // chip from the pixel split alone; on small images (at most 32768 pixels, 512 blocks
-        // of 64) single tiles win: more workgroups, and at 204 or fewer registers two
-        // wavefronts per SIMD.  Two input-channel tiles (336 registers, one wavefront per
+        // chip from the pixel split alone; on small images (at most 32768 pixels) single
+        // tiles win: more workgroups, and at 204 or fewer registers two wavefronts per
+        // SIMD.  Two input-channel tiles (336 registers, one wavefront per
         // SIMD) measured slower at every layer size of the surrogate network.
         P.co_t = npix > 32768 && Cout % 64 == 0 ? 2 : 1;
         P.ci_t = 1;
-        // Four sub-groups per workgroup (their accumulators added in LDS, a quarter of the
-        // partials) where one 32-channel output tile meets several input tiles on a large
-        // image: the surrogate's 96 -> 32 at 8 x 256^2, 103 -> 86 us.  Elsewhere they
-        // measured level or slower: the pixel split's parallelism matters more than the
-        // partials' bytes.
-        P.sub = P.pb == 64 && Cout == 32 && Cin >= 64 && npix >= 262144 ? 4 : 1;
         const int64_t groups = (int64_t)(Cin / (32 * P.ci_t)) * (Cout / (32 * P.co_t));
         const int64_t nblocks = npix / P.pb;
-        // about kWgradGroups three-wavefront sub-groups; half as many, with twice the pixels
-        // each, where several channel tiles split a large image (the surrogate's 64 -> 64
-        // and 192 -> 64 at 8 x 128^2: 8-22% faster)
-        const int64_t target = (P.sub == 1 && groups >= 2 && npix >= 131072 ? kWgradGroups / 2 : kWgradGroups) / P.sub;
+        // about kWgradGroups three-wavefront workgroups; half as many, with twice the pixels
+        // each, where several channel tiles split a large image (64 -> 64 and 192 -> 64 at
+        // 8 x 128^2 with 64-pixel blocks: 8-22% faster)
+        const int64_t target = groups >= 2 && npix >= 131072 ? kWgradGroups / 2 : kWgradGroups;
         // bytes read: each workgroup stages its input-channel and output-channel slices
         const double reads = 2.0 * (double)npix *
                              ((double)Cin * (Cout / (32 * P.co_t)) + (double)Cout * (Cin / (32 * P.ci_t)));
@@ -1248,7 +1418,6 @@ WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout)
         int64_t nchunk = (target + groups - 1) / groups;
         nchunk = std::max<int64_t>(1, std::min<int64_t>({nchunk, cap, nblocks}));
         P.per_chunk = (nblocks + nchunk - 1) / nchunk;
-        P.per_chunk = (P.per_chunk + P.sub - 1) / P.sub * P.sub;
         P.nchunk = (nblocks + P.per_chunk - 1) / P.per_chunk;
     } else {
         // gather kernel: about kWgradWaves single-wave workgroups, chunks of >= 256 pixels
@@ -1270,17 +1439,11 @@ int launch_wgrad_lds(const WgradPlan &P, const __bf16 *in, int N, int H, int W, 
 {
     const dim3 grid((unsigned)((Cin / (32 * P.ci_t)) * (Cout / (32 * P.co_t))), (unsigned)P.nchunk);
     const int bpc = (int)P.per_chunk;
-#define DDF_WGRAD_LAUNCH(CO, CI, S)                                                                                \
-    hipLaunchKernelGGL((k_wgrad_lds<PB, CO, CI, S>), grid, dim3(192 * S), 0, st, in, N, H, W, Cin, in_cs, in_co, dout, \
-                       Cout, d_cs, bpc, part, bpart, cstride)
-    if (P.co_t == 2) {
-        DDF_WGRAD_LAUNCH(2, 1, 1);
-    } else if constexpr (PB == 64) {
-        if (P.sub == 4) DDF_WGRAD_LAUNCH(1, 1, 4);
-        else DDF_WGRAD_LAUNCH(1, 1, 1);
-    } else {
-        DDF_WGRAD_LAUNCH(1, 1, 1);
-    }
+#define DDF_WGRAD_LAUNCH(CO, CI)                                                                              \
+    hipLaunchKernelGGL((k_wgrad_lds<PB, CO, CI>), grid, dim3(192), 0, st, in, N, H, W, Cin, in_cs, in_co, dout, Cout, \
+                       d_cs, bpc, part, bpart, cstride)
+    if (P.co_t == 2) DDF_WGRAD_LAUNCH(2, 1);
+    else DDF_WGRAD_LAUNCH(1, 1);
 #undef DDF_WGRAD_LAUNCH
     return DDF_OK;
 }
@@ -1293,9 +1456,9 @@ size_t ddf_nn_wgrad_workspace_bytes(int32_t N, int32_t H, int32_t W, int32_t Cin
 {
     const int64_t npix = (int64_t)N * H * W;
     const WgradPlan P = wgrad_plan(N, H, W, Cin, Cout);
-    if (chunk_out) *chunk_out = (int32_t)(P.lds ? P.per_chunk * P.pb : P.per_chunk);
+    if (chunk_out) *chunk_out = (int32_t)(P.roll || P.lds ? P.per_chunk * P.pb : P.per_chunk);
     const int64_t wsz = (int64_t)9 * Cout * Cin;
-    if (P.lds) return (size_t)(P.nchunk * (wsz + Cout)) * sizeof(float);
+    if (P.roll || P.lds) return (size_t)(P.nchunk * (wsz + Cout)) * sizeof(float);
     const int64_t bsz = ((npix + 255) / 256) * Cout;
     return (size_t)std::max(P.nchunk * wsz, bsz) * sizeof(float);
 }
@@ -1318,12 +1481,26 @@ int ddf_nn_conv3x3_wgrad(const void *in, int32_t N, int32_t H, int32_t W, int32_
     float *part = (float *)workspace;
     const __bf16 *ib = (const __bf16 *)in, *db16 = (const __bf16 *)dout;
     const int64_t wsz = (int64_t)9 * Cout * Cin;
+    if (P.roll) {
+        // strip c holds its weight partials, then (with db) its bias partials
+        const int64_t cs = wsz + (db ? Cout : 0);
+        float *bpart = db ? part + wsz : nullptr;
+        const dim3 grid((unsigned)(P.nchunk * (Cin / 32) * (Cout / 32)));
+        const int rows = (int)P.per_chunk;
+        if (P.pb == 128)
+            hipLaunchKernelGGL(k_wgrad_roll<128>, grid, dim3(256), 0, st, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs,
+                               rows, part, bpart, cs);
+        else
+            hipLaunchKernelGGL(k_wgrad_roll<64>, grid, dim3(256), 0, st, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs,
+                               rows, part, bpart, cs);
+        sum_chunks(part, cs, cs, (int)P.nchunk, dw, wsz, db, accumulate, st);
+        return check_launch();
+    }
     if (P.lds) {
         // chunk c holds its weight partials, then (with db) its bias partials
         const int64_t cs = wsz + (db ? Cout : 0);
         float *bpart = db ? part + wsz : nullptr;
-        if (P.pb == 64) launch_wgrad_lds<64>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, cs, st);
-        else if (P.pb == 32) launch_wgrad_lds<32>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, cs, st);
+        if (P.pb == 32) launch_wgrad_lds<32>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, cs, st);
         else launch_wgrad_lds<16>(P, ib, N, H, W, Cin, in_cs, in_co, db16, Cout, d_cs, part, bpart, cs, st);
         sum_chunks(part, cs, cs, (int)P.nchunk, dw, wsz, db, accumulate, st);
         return check_launch();

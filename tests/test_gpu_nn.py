@@ -487,12 +487,14 @@ def test_cavity_input_channels(C, off):
 
 
 @pytest.mark.parametrize("B,H,W,Cin,Cout", [
-    (1, 4, 64, 64, 64),      # 64-pixel blocks, single 32 x 32 tiles (small image)
-    (1, 3, 128, 96, 32),     # 64-pixel blocks, single tiles (96 input channels)
+    (1, 4, 64, 64, 64),      # row streaming, 64-pixel columns, one strip (small image)
+    (1, 3, 128, 96, 32),     # row streaming, 128-pixel columns, 96 input channels
+    (1, 1, 64, 32, 32),      # row streaming, a single row: both neighbour rows are padding
+    (3, 37, 192, 64, 96),    # row streaming, 64-pixel columns, 3 x 6 tiles, ragged strips
     (2, 5, 32, 32, 64),      # 32-pixel blocks, single tiles
     (1, 2, 16, 128, 256),    # 16-pixel blocks, single tiles over 4 x 8 tile groups
-    (1, 129, 256, 32, 64),   # more than 32768 pixels: 64-pixel blocks, two output tiles per wavefront
-    (2, 17, 1024, 64, 128),  # two output tiles, 2 x 2 tile groups
+    (1, 129, 256, 32, 64),   # row streaming, strips of 8 rows, the last one of a single row
+    (2, 17, 1024, 64, 128),  # row streaming, 8 columns per image, 2 x 4 tiles
     (1, 1040, 32, 32, 64),   # 32-pixel blocks, two output tiles
     (2, 4, 8, 32, 32),       # rows of 8: the gather kernel
 ])
@@ -591,17 +593,19 @@ def test_conv3x3_lds_configs(B, H, W, Cin, Cout, cs_in, co_in, cs_out, co_out, a
     assert np.array_equal(got[..., untouched], out0q[..., untouched])
 
 
-def test_weight_gradient_with_sub_groups_and_a_ragged_last_chunk():
-    # 64 -> 32 channels on 2 x 683 x 192 pixels: four sub-groups per workgroup, whose
-    # accumulators are added in LDS; the last chunk's 6 blocks leave two sub-groups a turn
-    # of zeros.  Every entry against the float64 sum over all pixels.
+def test_row_streaming_weight_gradient_with_ragged_strips():
+    # 64 -> 32 channels on 2 x 683 x 192 pixels: three 64-pixel columns per image, strips of
+    # 32 rows, the last one of each column 11 rows long.  Every entry against the float64
+    # sum over all pixels.
     B, H, W, Cin, Cout = 2, 683, 192, 64, 32
     r = np.random.default_rng(77)
     xt, x = bf(r.standard_normal((B, H, W, Cin)))
     dyt, dy = bf(r.standard_normal((B, H, W, Cout)))
     chunk = C.c_int32()
     nbytes = L.lib().ddf_nn_wgrad_workspace_bytes(B, H, W, Cin, Cout, C.byref(chunk))
-    assert (B * H * W // 64) % (chunk.value // 64) == 6
+    rows = chunk.value // 64
+    assert chunk.value % 64 == 0 and H % rows == 11
+    assert nbytes == B * 3 * (H // rows + 1) * (9 * Cout * Cin + Cout) * 4
     ws = torch.empty(nbytes, dtype=torch.uint8, device=DEV)
     dw = torch.empty(9 * Cout * Cin, dtype=torch.float32, device=DEV)
     db = torch.empty(Cout, dtype=torch.float32, device=DEV)
@@ -622,9 +626,9 @@ def test_weight_gradient_with_sub_groups_and_a_ragged_last_chunk():
 
 
 @pytest.mark.parametrize("H,Cin,Cout", [
-    (256, 32, 32),     # 32 -> 32 at 256^2: 256-pixel convolution segments, single-tile weight gradient
+    (256, 32, 32),     # 32 -> 32 at 256^2: 256-pixel convolution segments, row-streaming weight gradient
     (256, 96, 32),     # the level-0 decoder input: 128-pixel segments
-    (128, 64, 64),     # 64-pixel segments x 2 channel tiles; weight gradient with two output tiles
+    (128, 64, 64),     # 64-pixel segments x 2 channel tiles; weight gradient over 2 x 2 tiles
     (64, 384, 128),    # the level-2 decoder input: 4 channel tiles
     (128, 192, 64),    # the level-1 decoder input
     (32, 256, 256),    # the bottom level: 32-pixel segments
