@@ -29,6 +29,14 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 using ddf::host::fail;
 
 __device__ __forceinline__ bf16x8 load8(const __bf16 *p) { return *(const bf16x8 *)p; }
+// Sixteen zero bytes in device memory.  A staging load whose pixel lies outside the image
+// (or whose lane has nothing to stage) reads these instead of being skipped: with every
+// load unconditional the compiler counts the loads still in flight exactly and waits for
+// just the ones a write to LDS needs, where a skipped load (a branch) made it wait for all
+// of them, the prefetched rows included.  The array is global memory (not const, which
+// would place it in another address space and make the selected pointer a flat one); it
+// is never written.
+__device__ __align__(16) __bf16 kZero8[8] = {};
 
 __device__ __forceinline__ bf16x8 zero8()
 {
@@ -136,7 +144,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(const __bf16 *__restrict__
     constexpr int XV = (PB + 2) * 4;             // 16-byte input vectors per staged row
     constexpr int NXV = (XV + 255) / 256;
     bf16x8 xr[PD][NXV];
-    // input row y0 - 1 + j of chunk c0 into register slot d
+    // input row y0 - 1 + j of chunk c0 into register slot d (zeros outside the image)
     auto fetch_row = [&](int d, int j, int c0) {
         const int yi = y0 - 1 + j;
         const bool row_ok = yi >= 0 && yi < H;
@@ -144,9 +152,8 @@ __global__ __launch_bounds__(256) void k_conv3x3_rows(const __bf16 *__restrict__
         for (int i = 0; i < NXV; ++i) {
             const int v = tid + 256 * i;
             const int c8 = v & 3, px = v >> 2, xx = x0 + px - 1;
-            xr[d][i] = zero8();
-            if (v < XV && row_ok && xx >= 0 && xx < W)
-                xr[d][i] = load8(in + ((img * H + yi) * W + xx) * in_cs + in_co + c0 + 8 * c8);
+            const bool ok = v < XV && row_ok && xx >= 0 && xx < W;
+            xr[d][i] = load8(ok ? in + ((img * H + yi) * W + xx) * in_cs + in_co + c0 + 8 * c8 : kZero8);
         }
     };
     // B operands of a chunk: lane (m, half) holds output channel co0 + m, input channels
@@ -279,16 +286,14 @@ __global__ __launch_bounds__(256) void k_conv3x3_lds(const __bf16 *__restrict__ 
         for (int i = 0; i < NXV; ++i) {
             const int v = tid + 256 * i;
             const int c8 = v & 3, px = v >> 2, xx = x0 + px - 1;
-            xr[i] = zero8();
-            if (v < XV && row_ok && xx >= 0 && xx < W)
-                xr[i] = load8(in + ((row + dy - 1) * W + xx) * in_cs + in_co + c0 + 8 * c8);
+            const bool ok = v < XV && row_ok && xx >= 0 && xx < W;
+            xr[i] = load8(ok ? in + ((row + dy - 1) * W + xx) * in_cs + in_co + c0 + 8 * c8 : kZero8);
         }
 #pragma unroll
         for (int i = 0; i < NWV; ++i) {
             const int v = tid + 256 * i;
             const int c8 = v & 3, q = v >> 2, co = q % (32 * NCO), dx = q / (32 * NCO);
-            wr[i] = zero8();
-            if (v < WV) wr[i] = load8(wt + ((int64_t)(3 * dy + dx) * Cout + co0 + co) * Cin + c0 + 8 * c8);
+            wr[i] = load8(v < WV ? wt + ((int64_t)(3 * dy + dx) * Cout + co0 + co) * Cin + c0 + 8 * c8 : kZero8);
         }
     };
     fetch(0);
@@ -488,16 +493,14 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(const __bf16 *__restrict__ in
             const int c8 = v % (4 * CI_T), q = v / (4 * CI_T);
             const int px = q % (PB + 2), rr = q / (PB + 2);
             const int yy = y + rr - 1, xx = x0 + px - 1;
-            xr[i] = zero8();
-            if (ok && v < XV && yy >= 0 && yy < H && xx >= 0 && xx < W)
-                xr[i] = load8(in + ((row + rr - 1) * W + xx) * in_cs + in_co + ci0 + 8 * c8);
+            const bool in_ok = ok && v < XV && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            xr[i] = load8(in_ok ? in + ((row + rr - 1) * W + xx) * in_cs + in_co + ci0 + 8 * c8 : kZero8);
         }
 #pragma unroll
         for (int i = 0; i < NDV; ++i) {
             const int v = t + 192 * i;
             const int c8 = v % (4 * CO_T), px = v / (4 * CO_T);
-            dr[i] = zero8();
-            if (ok && v < DV) dr[i] = load8(dout + (row * W + x0 + px) * d_cs + co0 + 8 * c8);
+            dr[i] = load8(ok && v < DV ? dout + (row * W + x0 + px) * d_cs + co0 + 8 * c8 : kZero8);
         }
     };
     if (b0 < b1) fetch(b0);
@@ -636,9 +639,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
         for (int i = 0; i < NIV; ++i) {
             const int e = t + 256 * i;
-            v[i] = zero8();
-            if (e < PB * 4 && yy >= 0 && yy < H)
-                v[i] = load8(in + (((int64_t)n * H + yy) * W + x0 + (e >> 2)) * in_cs + in_co + ci0 + 8 * (e & 3));
+            const bool ok = e < PB * 4 && yy >= 0 && yy < H;
+            v[i] = load8(ok ? in + (((int64_t)n * H + yy) * W + x0 + (e >> 2)) * in_cs + in_co + ci0 + 8 * (e & 3)
+                            : kZero8);
         }
     };
     auto store_in = [&](const bf16x8 (&v)[NIV], int slot) {
@@ -654,9 +657,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         for (int i = 0; i < NDV; ++i) {
             const int e = t + 256 * i;
             const int xx = x0 - 1 + (e >> 2);
-            dr[i] = zero8();
-            if (e < (PB + 2) * 4 && xx >= 0 && xx < W)
-                dr[i] = load8(dout + (((int64_t)n * H + y) * W + xx) * d_cs + co0 + 8 * (e & 3));
+            const bool ok = e < (PB + 2) * 4 && xx >= 0 && xx < W;
+            dr[i] = load8(ok ? dout + (((int64_t)n * H + y) * W + xx) * d_cs + co0 + 8 * (e & 3) : kZero8);
         }
         fetch_in(ir, y + 1);
     };
