@@ -184,6 +184,25 @@ def test_weight_gradient_rejects_bad_arguments_before_any_launch():
         assert needle in lib.ddf_last_error().decode()
 
 
+@pytest.mark.parametrize("N,H,W,Cin,Cout,pixels_per_strip,strips", [
+    (8, 256, 256, 32, 32, 128 * 8, 8 * 2 * 32),      # 128-pixel columns, strips of 8 rows: 512 workgroups
+    (8, 256, 256, 96, 32, 128 * 32, 8 * 2 * 8),      # three channel tiles: 32 rows, 384 workgroups
+    (8, 128, 128, 192, 64, 128 * 32, 8 * 1 * 4),     # twelve tiles: 32 rows, 384 workgroups
+    (8, 64, 64, 384, 128, 64 * 64, 8 * 1 * 1),       # 64-pixel columns, 48 tiles: whole images, 384 workgroups
+    (1, 4, 64, 64, 64, 64 * 4, 1),                   # a strip no taller than the image
+    (2, 683, 192, 64, 32, 64 * 32, 2 * 3 * 22),      # 64-pixel columns (192 is no multiple of 128), ragged strips
+])
+def test_row_streaming_weight_gradient_plan(N, H, W, Cin, Cout, pixels_per_strip, strips):
+    # Widths that are multiples of 64 take the row-streaming weight gradient: strips of 8,
+    # 16, 32, ... rows, the shortest that leave at most 512 workgroups (one per strip and
+    # 32 x 32 channel tile).  Its workspace holds one set of weight and bias partials per
+    # strip.
+    chunk = C.c_int32()
+    nbytes = L.lib().ddf_nn_wgrad_workspace_bytes(N, H, W, Cin, Cout, C.byref(chunk))
+    assert chunk.value == pixels_per_strip
+    assert nbytes == strips * (9 * Cout * Cin + Cout) * 4
+
+
 def test_cast_weights_multi_rejects_bad_tables_before_any_launch():
     lib = L.lib()
     ok = L.CastLayer(1 << 20, 2 << 20, 3 << 20, 32, 32, 32, 32)
