@@ -1030,7 +1030,7 @@ __global__ __launch_bounds__(256) void k_mse(const __bf16 *__restrict__ out, int
                                              int64_t npix, float w0, float w1, float w2, float w3,
                                              __bf16 *__restrict__ dout, double *__restrict__ part, int vec)
 {
-    __shared__ double sh[256];
+    __shared__ double sh[4];
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double acc = 0.0;
     if (p < npix) {
@@ -1038,9 +1038,11 @@ __global__ __launch_bounds__(256) void k_mse(const __bf16 *__restrict__ out, int
         if (vec) {   // 16-byte rows: the first vector carries the gradient, the rest zeros
             bf16x8 g = zero8();
             const bf16x8 o = load8(out + p * o_cs);
+            const float4 t4 = *(const float4 *)(target + p * 4);
+            const float tv[4] = {t4.x, t4.y, t4.z, t4.w};
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const float d = (float)o[c] - target[p * 4 + c];
+                const float d = (float)o[c] - tv[c];
                 acc += (double)wc[c] * (double)d * (double)d;
                 g[c] = (__bf16)(2.0f * wc[c] * d / (float)npix);
             }
@@ -1058,13 +1060,13 @@ __global__ __launch_bounds__(256) void k_mse(const __bf16 *__restrict__ out, int
             }
         }
     }
-    sh[threadIdx.x] = acc;
+    // fixed-order sums: a halving tree within each wavefront, then the four wavefront
+    // sums in order
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) acc += __shfl_down(acc, s, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) part[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
 // out[0] = (sum of part[0 .. n)) / div: thread t sums part[t], part[t + 256], ... in order,
@@ -1206,6 +1208,22 @@ __global__ void k_cavity_inputs(const float *__restrict__ re, const float *__res
     } else {
         for (int c = 0; c < C; ++c) x[pix * C + c] = (__bf16)cavity_channel(c, px, py, W, H, lre, un);
     }
+}
+
+// The same on a grid of pixel rows (C % 8 == 0, x 16-byte aligned): each block takes its
+// row (image, y) once, a lane its pixel and group of 8 channels by a shift, so no lane
+// divides 64-bit indices.
+__global__ void k_cavity_inputs8(const float *__restrict__ re, const float *__restrict__ u, const RowGrid g, int H,
+                                 int W, int C, float lre_lo, float lre_hi, float u_ref, __bf16 *__restrict__ x)
+{
+    int row, px, c;
+    if (!row_item(g, row, px, c)) return;
+    const int n = row / H, py = row - n * H;
+    const float lre = (logf(re[n]) - lre_lo) / (lre_hi - lre_lo), un = u[n] / u_ref;
+    bf16x8 v;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = (__bf16)cavity_channel(c + k, px, py, W, H, lre, un);
+    store8(x + ((int64_t)row * W + px) * C + c, v);
 }
 
 // Normalised training targets from steady fields (dense FP64 [N][H][W] each):
@@ -1619,7 +1637,7 @@ int ddf_nn_mse(const void *out, int32_t o_cs, const float *target, int64_t npix,
     hipStream_t st = (hipStream_t)stream;
     const int nb = (int)((npix + 255) / 256);
     double *part = (double *)workspace;
-    const int vec = o_cs % 8 == 0 && al16(out) && al16(dout);
+    const int vec = o_cs % 8 == 0 && al16(out) && al16(dout) && al16(target);
     hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, (const __bf16 *)out, o_cs, target, npix, weights4[0],
                        weights4[1], weights4[2], weights4[3], (__bf16 *)dout, part, vec);
     hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, st, part, nb, (double)npix, loss_dev);
@@ -1725,6 +1743,13 @@ int ddf_nn_cavity_inputs(const float *re, const float *u, int32_t N, int32_t H, 
     if (C < 5) return fail(DDF_ERR_ARG, "cavity_inputs: at least 5 channels");
     if (N < 0 || H < 1 || W < 1) return fail(DDF_ERR_ARG, "cavity_inputs: bad shape");
     const int vec = C % 8 == 0 && al16(x);
+    if (N == 0) return DDF_OK;
+    if (vec && row_grid_fits((int64_t)N * H, W, C)) {
+        const RowGrid g = row_grid(W, C);
+        hipLaunchKernelGGL(k_cavity_inputs8, dim3((unsigned)(N * H * g.bpr)), dim3(256), 0, (hipStream_t)stream, re, u, g,
+                           H, W, C, std::log(re_lo), std::log(re_hi), u_ref, (__bf16 *)x);
+        return check_launch();
+    }
     hipLaunchKernelGGL(k_cavity_inputs, dim3(blocks_for((int64_t)N * H * W * (vec ? C / 8 : 1))), dim3(256), 0,
                        (hipStream_t)stream, re, u, N, H, W, C, std::log(re_lo), std::log(re_hi), u_ref, (__bf16 *)x, vec);
     return check_launch();
