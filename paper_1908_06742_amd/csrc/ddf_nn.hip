@@ -574,12 +574,12 @@ __global__ __launch_bounds__(192) void k_wgrad_lds(const __bf16 *__restrict__ in
 // workgroup.  dW[dy][dx][co][ci] = sum over output pixels q of dout[q][co] in[q + (dy, dx)][ci]
 // is summed as sum over input pixels p of dout[p - (0, dx)][co] in[p + (dy, 0)][ci]: across
 // the blocks of a row p covers [0, W) exactly, and the terms the substitution adds or drops
-// have a zero factor (dout outside the image, or the convolution's zero padding).  A
-// sub-group of four wavefronts walks a strip of output rows y0 .. y1-1 of one PB-pixel
-// column; per row it stages the output-gradient row with a one-pixel halo and the next input
-// row, which joins the two before it in a ring of three, so every input row is read from
-// memory once per strip (plus two rows of halo).  Wavefront w of the sub-group takes the
-// 16-pixel steps k0 = 16 (w + 4 i) of the row; per step it reads the three dx-shifted
+// have a zero factor (dout outside the image, or the convolution's zero padding).  The
+// workgroup's four wavefronts walk a strip of output rows y0 .. y1-1 of one PB-pixel
+// column; per row they stage the output-gradient row with a one-pixel halo and the next
+// input row, which joins the two before it in a ring of three, so every input row is read
+// from memory once per strip (plus two rows of halo).  Wavefront w takes the 16-pixel
+// steps k0 = 16 (w + 4 i) of the row; per step it reads the three dx-shifted
 // output-gradient operands and the three input rows' operands once and issues the nine tap
 // products (A = output gradient, B = input, both by transpose reads).  The next row's loads
 // are in flight during the current row's products, and the strip's first rows are requested
