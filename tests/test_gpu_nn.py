@@ -593,6 +593,30 @@ def test_conv3x3_lds_configs(B, H, W, Cin, Cout, cs_in, co_in, cs_out, co_out, a
     assert np.array_equal(got[..., untouched], out0q[..., untouched])
 
 
+@pytest.mark.parametrize("W,Cin,d_cs,d_co", [
+    (128, 32, 96, 64),    # 128-pixel columns: the skip slice of a level-0 concatenation gradient
+    (192, 64, 160, 32),   # 64-pixel columns, two input tiles, a slice in the middle
+])
+def test_row_streaming_weight_gradient_of_channel_slices(W, Cin, d_cs, d_co):
+    # The surrogate's weight gradients read the output gradient as a channel slice of a
+    # wider buffer (offset through the pointer, stride d_cs) and the input as a slice too;
+    # against the float64 sums over all pixels, with accumulation into dw and db.
+    B, H, Cout = 2, 19, 32
+    r = np.random.default_rng(W + Cin + d_co)
+    cs = Cin + 16
+    xt, x = bf(r.standard_normal((B, H, W, cs)))
+    dyt, dy = bf(r.standard_normal((B, H, W, d_cs)))
+    xs_, d2 = x[..., 8:8 + Cin], dy[..., d_co:d_co + Cout]
+    _, rdw, rdb = U.conv3x3_backward(xs_, np.zeros((9, Cout, Cin)), d2)
+    ws = torch.empty(L.lib().ddf_nn_wgrad_workspace_bytes(B, H, W, Cin, Cout, None), dtype=torch.uint8, device=DEV)
+    dw = torch.full((9 * Cout * Cin,), -1.0, dtype=torch.float32, device=DEV)
+    db = torch.full((Cout,), 2.0, dtype=torch.float32, device=DEV)
+    dptr = C.c_void_p(dyt.data_ptr() + 2 * d_co)
+    L.check(L.lib().ddf_nn_conv3x3_wgrad(p(xt), B, H, W, Cin, cs, 8, dptr, Cout, d_cs, p(dw), p(db), 1, p(ws), s0()))
+    assert rel(dw.cpu().numpy().reshape(9, Cout, Cin) + 1.0, rdw) < 1e-5
+    assert rel(db.cpu().numpy() - 2.0, rdb) < 1e-5
+
+
 def test_row_streaming_weight_gradient_with_ragged_strips():
     # 64 -> 32 channels on 2 x 683 x 192 pixels: three 64-pixel columns per image, strips of
     # 32 rows, the last one of each column 11 rows long.  Every entry against the float64
