@@ -491,6 +491,8 @@ def test_cavity_input_channels(C, off):
     (1, 3, 128, 96, 32),     # row streaming, 128-pixel columns, 96 input channels
     (1, 1, 64, 32, 32),      # row streaming, a single row: both neighbour rows are padding
     (3, 37, 192, 64, 96),    # row streaming, 64-pixel columns, 3 x 6 tiles, ragged strips
+    (1, 3, 64, 32, 256),     # row streaming, the most output channels (8 output tiles)
+    (1, 2, 128, 256, 32),    # row streaming, 8 input tiles, the bias from the first only
     (2, 5, 32, 32, 64),      # 32-pixel blocks, single tiles
     (1, 2, 16, 128, 256),    # 16-pixel blocks, single tiles over 4 x 8 tile groups
     (1, 129, 256, 32, 64),   # row streaming, strips of 8 rows, the last one of a single row
